@@ -1,0 +1,332 @@
+"""Pins for the CPU oracle: each test checks it against something other than itself --
+hand-derived values, exact arithmetic, brute force, closed forms, invariants, a library
+routine, or a finite difference -- so that a dropped term, a wrong sign, a wrong lag or a
+transposed operand fails at least one of them."""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --- embedding (Sec. II-B) --------------------------------------------------------------
+def test_embed_closed_form():
+    x = np.arange(10, 17, dtype=np.float32)  # x(t) = 10 + t, L = 7
+    got = O.embed(x, E=3, tau=2)
+    # points t = 4, 5, 6; coordinates x(t), x(t-2), x(t-4)
+    want = np.array([[14, 12, 10], [15, 13, 11], [16, 14, 12]], dtype=np.float32)
+    assert np.array_equal(got, want)
+    assert O.embed(x, E=1, tau=1).ravel().tolist() == x.tolist()
+    assert O.embed(x, E=8, tau=1).shape == (0, 8)
+
+
+# --- canonical FP32 squared distance -------------------------------------------------
+def test_sqdist_exact_on_small_integers():
+    # Small integers: every FP32 operation is exact, so d^2 must equal the exact sum.
+    rng = np.random.default_rng(0)
+    x = rng.integers(-20, 21, size=40).astype(np.float32)
+    for E, tau in [(1, 1), (3, 1), (4, 2), (7, 3)]:
+        Q, C, _ = O.point_sets(40, E, tau, 0)
+        D2 = O.sqdist_fp32(x, Q, C, E, tau)
+        xi = [int(v) for v in x]
+        for a, t in enumerate(Q[::3]):
+            for b, s in enumerate(C[::5]):
+                exact = sum((xi[t - e * tau] - xi[s - e * tau]) ** 2 for e in range(E))
+                assert D2[3 * a, 5 * b] == exact
+
+
+def test_sqdist_order_lag0_first_no_fma():
+    # delta_0 = 1, delta_1 = delta_2 = 2^-12.  Lag 0 first: fl(1 + 2^-24) = 1 twice -> 1.
+    # (Lag E-1 first would give 1 + 2^-23; a fused multiply-add would keep 2^-24 terms.)
+    h = np.float32(2.0 ** -12)
+    x_t = np.array([0.0, 0.0, 0.0], dtype=np.float32)  # x(t-2), x(t-1), x(t)
+    x_s = np.array([-h, -h, -1.0], dtype=np.float32)   # x(s-2), x(s-1), x(s)
+    x = np.concatenate([x_s, x_t])                     # s = 2, t = 5
+    D2 = O.sqdist_fp32(x, [5], [2], E=3, tau=1)
+    assert D2[0, 0] == np.float32(1.0)
+
+
+def test_sqdist_within_rounding_bound():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(60).astype(np.float32)
+    E = 6
+    Q, C, _ = O.point_sets(60, E, 1, 0)
+    D2 = O.sqdist_fp32(x, Q, C, E, 1)
+    u = 2.0 ** -24
+    for a in range(0, len(Q), 7):
+        for b in range(0, len(C), 5):
+            t, s = Q[a], C[b]
+            ex = sum((Fraction(float(x[t - e])) - Fraction(float(x[s - e]))) ** 2 for e in range(E))
+            # each of E subtractions, E products, E-1 additions rounds once
+            assert abs(Fraction(float(D2[a, b])) - ex) <= Fraction((3 * E + 1) * u) * ex + Fraction(0)
+
+
+# --- neighbour selection (Alg. 3 / Alg. 4) ----------------------------------------------
+def _brute_knn(xi, E, tau, Tp, k):
+    """Pure-Python exact brute force on integer series: sort (d^2, s) tuples."""
+    L = len(xi)
+    lo = (E - 1) * tau
+    Q = list(range(lo, L - Tp))
+    out = {}
+    for t in Q:
+        cand = []
+        for s in Q:
+            if s == t:
+                continue
+            d2 = sum((xi[t - e * tau] - xi[s - e * tau]) ** 2 for e in range(E))
+            cand.append((d2, s))
+        cand.sort()
+        out[t] = [s for _, s in cand[:k]]
+    return out
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_knn_matches_brute_force_with_ties(seed):
+    rng = np.random.default_rng(seed)
+    L = 48
+    # a few distinct small integers: many exact ties and zero distances
+    xi = rng.integers(0, 4, size=L).tolist()
+    x = np.array(xi, dtype=np.float32)
+    for E in (1, 2, 3, 5):
+        for tau in (1, 2):
+            for Tp in (0, 1):
+                Q, idx, w, d2 = O.knn_table(x, E, tau, Tp)
+                bf = _brute_knn(xi, E, tau, Tp, E + 1)
+                for r, t in enumerate(Q):
+                    assert idx[r].tolist() == bf[int(t)], (E, tau, Tp, t)
+
+
+def test_knn_sets_match_kdtree_away_from_near_ties():
+    from scipy.spatial import cKDTree
+
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(300).astype(np.float32)
+    for E in (2, 4, 7):
+        Q, idx, w, d2 = O.knn_table(x, E, 1, 0)
+        V = O.embed(x.astype(np.float64), E, 1)
+        tree = cKDTree(V)
+        dist, nb = tree.query(V, k=E + 3)
+        checked = 0
+        for r in range(len(Q)):
+            nbr = [int(n) for n in nb[r] if n != r][: E + 2]
+            dd = [float(dv) for n, dv in zip(nb[r], dist[r]) if n != r][: E + 2]
+            if dd[E + 1] - dd[E] < 1e-5 * max(dd[E], 1e-30):
+                continue  # k-th and (k+1)-th too close to call in FP32
+            assert set((np.array(nbr[: E + 1]) + E - 1).tolist()) == set(idx[r].tolist())
+            checked += 1
+        assert checked > 0.9 * len(Q)
+
+
+def test_knn_rejects_k_beyond_candidates():
+    x = np.arange(6, dtype=np.float32)
+    with pytest.raises(ValueError):
+        O.knn_table(x, 5, 1, 0)  # 2 points, k = 6
+
+
+def test_knn_invariant_under_exact_transforms():
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(200).astype(np.float32)
+    for E in (1, 3, 6):
+        _, i0, _, _ = O.knn_table(x, E, 1, 0)
+        _, i1, _, _ = O.knn_table(-x, E, 1, 0)
+        _, i2, _, _ = O.knn_table(x * np.float32(8.0), E, 1, 0)
+        _, i3, _, _ = O.knn_table(x * np.float32(2.0 ** -5), E, 1, 0)
+        assert np.array_equal(i0, i1) and np.array_equal(i0, i2) and np.array_equal(i0, i3)
+
+
+# --- weights (Sec. III-A "normalize") --------------------------------------------------
+def test_weights_hand_worked():
+    with open(os.path.join(GOLDEN, "hand_worked_L5.json")) as f:
+        g = json.load(f)
+    x = np.array(g["x"], dtype=np.float32)
+    Q, idx, w, d2 = O.knn_table(x, g["E"], g["tau"], g["Tp"])
+    for row in g["rows"]:
+        r = list(Q).index(row["t"])
+        assert idx[r].tolist() == row["nbr"]
+        want = [eval(expr, {"exp": math.exp}) for expr in row["w"]]
+        np.testing.assert_allclose(w[r], want, rtol=0, atol=1e-15)
+
+
+def test_weights_equal_distances_uniform():
+    x = np.array([0, 1, -1, 2, -2, 1, -1], dtype=np.float32)
+    w = O.weights_fp64(x, 0, [1, 2, 5], 1, 1)
+    np.testing.assert_allclose(w, [1 / 3, 1 / 3, 1 / 3], atol=1e-15)
+
+
+def test_weights_zero_distance_limit():
+    x = np.array([0, 5, 0, 5, 1, 0], dtype=np.float32)
+    w = O.weights_fp64(x, 0, [2, 5, 4], 1, 1)  # d = 0, 0, 1
+    np.testing.assert_array_equal(w, [0.5, 0.5, 0.0])
+    assert np.all(np.isfinite(w))
+
+
+# --- Pearson --------------------------------------------------------------------------
+def test_pearson_closed_forms_and_library():
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal(500)
+    b = 0.3 * a + rng.standard_normal(500)
+    assert abs(O.pearson(a, b) - np.corrcoef(a, b)[0, 1]) < 1e-13
+    assert abs(O.pearson(a, 2 * a + 1) - 1.0) < 1e-14
+    assert abs(O.pearson(a, -a) + 1.0) < 1e-14
+    assert math.isnan(O.pearson(a, np.full(500, 3.0)))
+    assert math.isnan(O.pearson(np.ones(4), a[:4]))
+
+
+# --- whole cross-map ------------------------------------------------------------------
+def test_periodic_series_cross_map_exactly():
+    rng = np.random.default_rng(11)
+    L, P = 140, 7
+    x = synth.periodic(P, L, rng)
+    tab2 = rng.standard_normal(P).astype(np.float32)
+    y = tab2[np.arange(L) % P]                        # any function of phase
+    ts = np.stack([x, y, rng.standard_normal(L).astype(np.float32)], axis=1)
+    rho, idx, w, d2 = O.ccm_block(ts, [0], [2], 1, 0, 3)
+    assert abs(rho[0, 0] - 1.0) < 1e-12
+    assert abs(rho[0, 1] - 1.0) < 1e-12
+    assert rho[0, 2] < 0.9
+
+
+def test_target_affine_invariance_and_columns():
+    w = synth.make("logistic64", cache=False)
+    ts = w.panel
+    lib = [0, 5, 9]
+    E = [3, 4, 2]
+    rho, idx, wt, d2 = O.ccm_block(ts, lib, E, 1, 0, 8)
+    ts2 = ts.astype(np.float64).copy()
+    ts2[:, 3] = -2.5 * ts2[:, 3] + 7.0
+    rho2 = O.crossmap_rho(ts2, idx, wt, E, 1, 0, 8)
+    # both the observed y and the prediction (weights sum to 1) map through a y + b
+    np.testing.assert_allclose(rho2[:, 3], rho[:, 3], atol=1e-12)
+    np.testing.assert_allclose(np.delete(rho2, 3, 1), np.delete(rho, 3, 1), atol=0)
+    # duplicate and permuted targets
+    perm = [4, 4, 0, 7, 1]
+    ts3 = ts[:, perm]
+    rho3 = O.crossmap_rho(ts3, idx, wt, E, 1, 0, 5)
+    np.testing.assert_array_equal(rho3, rho[:, perm])
+
+
+def test_reuse_equals_per_pair_recompute():
+    """Alg. 2's one-table-per-library reuse gives exactly Alg. 1's per-pair result."""
+    w = synth.make("logistic64", cache=False)
+    ts = w.panel[:200, :6]
+    lib_E = [2, 3, 4, 3, 5, 2]
+    rho, idx, wt, d2 = O.ccm_block(ts, list(range(6)), lib_E, 1, 0, 6)
+    for i in range(6):
+        for j in range(6):
+            Q, ii, ww, _ = O.knn_table(ts[:, i], lib_E[i], 1, 0)  # rebuilt for this pair
+            y = ts[:, j].astype(np.float64)
+            r = O.pearson(y[Q], np.sum(ww * y[ii], axis=1))
+            assert r == rho[i, j]
+
+
+def test_self_cross_map_is_simplex_at_tp0():
+    w = synth.make("logistic64", cache=False)
+    ts = w.panel[:, :4]
+    lib_E = [2, 3, 5, 1]
+    rho, *_ = O.ccm_block(ts, list(range(4)), lib_E, 1, 0, 4)
+    for i in range(4):
+        assert abs(O.simplex_rho(ts[:, i], lib_E[i], 1, 0) - rho[i, i]) < 1e-14
+
+
+def test_optE_argmax_and_ties():
+    w = synth.make("logistic64", cache=False)
+    ts = w.panel[:300, :3]
+    optE, rho, nanf = O.simplex_optE(ts, [0, 1, 2], 1, 6, 1, 1)
+    for i in range(3):
+        best = np.nanmax(rho[i])
+        assert optE[i] == 1 + int(np.nonzero(rho[i] == best)[0][0])
+        assert not nanf[i]
+    # constant series: every skill is NaN -> E_min, flagged
+    c = np.ones((50, 1), dtype=np.float32)
+    o, r, f = O.simplex_optE(c, [0], 2, 4, 1, 1)
+    assert o[0] == 2 and f[0] and np.all(np.isnan(r))
+
+
+def test_half_mode_sets():
+    Q, C, excl = O.point_sets(20, 3, 1, 1, O.MODE_HALF)
+    assert C.tolist() == list(range(2, 9)) and Q.tolist() == list(range(12, 19)) and not excl
+
+
+def test_coupled_logistic_direction():
+    """CCM direction (Sec. II-B): if j drives i, i's manifold recovers j, so
+    rho[lib=i, tgt=j] exceeds rho[lib=j, tgt=i] on most one-way edges."""
+    from scipy.stats import binomtest
+
+    wins = 0
+    total = 0
+    for trial in (0, 1):
+        w = synth.make("logistic64", trial, cache=False)
+        ts = w.panel
+        b = w.beta
+        optE = np.full(64, 3, dtype=np.int32)
+        rho, *_ = O.ccm_block(ts, np.arange(64), optE, 1, 0, 64)
+        i, j = np.nonzero((b > 0.05) & (b.T == 0))
+        wins += int(np.sum(rho[i, j] > rho[j, i]))
+        total += len(i)
+    assert binomtest(wins, total, 0.5, alternative="greater").pvalue < 0.01
+
+
+# --- gradients --------------------------------------------------------------------------
+def _rho_fixed(ts64, lib_col, j, idx, E, tau, x_override=None):
+    """rho of one pair from oracle pieces with the neighbour sets held fixed."""
+    L = ts64.shape[0]
+    Q = np.arange((E - 1) * tau, L)
+    x = ts64[:, lib_col] if x_override is None else x_override
+    w = O.weights_rows_fp64(x, Q, idx, E, tau)
+    y = ts64[:, j]
+    return O.pearson(y[Q], np.sum(w * y[idx], axis=1))
+
+
+def test_gradient_invariants_and_finite_differences():
+    w = synth.make("logistic64", cache=False)
+    ts64 = w.panel[:160, :6].astype(np.float64)
+    lib_ids = [1, 4]
+    lib_E = [3, 2]
+    pairs = np.array([[0, 2], [1, 5], [0, 1]], dtype=np.int32)
+    gw = np.array([1.0, -0.5, 2.0])
+    idx, wt, d2 = O.knn(ts64.astype(np.float32), lib_ids, lib_E, 1, 0, 4)
+    g_tgt, g_lib = O.crossmap_rho_grad(ts64, lib_ids, lib_E, idx, 1, pairs, gw)
+    L = ts64.shape[0]
+    # target invariants: rho is invariant under y -> a y + b
+    for j in (1, 2, 5):
+        assert abs(g_tgt[:, j].sum()) < 1e-10
+        assert abs(np.dot(g_tgt[:, j], ts64[:, j])) < 1e-10
+    # library invariants: weights depend on x only through d_k / d_1
+    for i in range(2):
+        assert abs(g_lib[i].sum()) < 1e-10
+        assert abs(np.dot(g_lib[i], ts64[:, lib_ids[i]])) < 1e-10
+
+    def loss(ts_t, xs):
+        tot = 0.0
+        for (i, j), g in zip(pairs, gw):
+            E = lib_E[i]
+            Q = np.arange(E - 1, L)
+            tot += g * _rho_fixed(ts_t, lib_ids[i], j, idx[i][Q, : E + 1], E, 1, x_override=xs[i])
+        return tot
+
+    xs0 = [ts64[:, c].copy() for c in lib_ids]
+    h = 1e-6
+    rng = np.random.default_rng(0)
+    for s in rng.choice(L, 12, replace=False):
+        for j in (2, 5):
+            tp = ts64.copy(); tp[s, j] += h
+            tm = ts64.copy(); tm[s, j] -= h
+            fd = (loss(tp, xs0) - loss(tm, xs0)) / (2 * h)
+            assert abs(fd - g_tgt[s, j]) < 1e-6 * max(1.0, abs(g_tgt[s, j]))
+        for i in range(2):
+            xp = [v.copy() for v in xs0]; xp[i][s] += h
+            xm = [v.copy() for v in xs0]; xm[i][s] -= h
+            # the perturbation is far too small to change any neighbour set
+            for xv in (xp[i], xm[i]):
+                E = lib_E[i]
+                Q, ii, _, _ = O.knn_table(xv, E, 1, 0)
+                assert np.array_equal(ii, idx[i][Q, : E + 1])
+            fd = (loss(ts64, xp) - loss(ts64, xm)) / (2 * h)
+            assert abs(fd - g_lib[i, s]) < 1e-6 * max(1.0, abs(g_lib[i, s]))
