@@ -1,0 +1,189 @@
+/*
+ * ccm.h -- C ABI of the MI355X (gfx950) all-pairs Convergent Cross Mapping hot path.
+ *
+ * The method is the one of Watanakeesuntorn et al., "Massively Parallel Causal Inference
+ * of Whole Brain Dynamics at Single Neuron Resolution" (IEEE eScience 2020):
+ *   - delay embedding of each series (Sec. II-B);
+ *   - an exact k-nearest-neighbour table per library series, k = E + 1 (Sec. III-B,
+ *     Alg. 3 / Alg. 4), turned into exponential weights normalised per row
+ *     (Sec. III-A, "normalize");
+ *   - optimal E per series by simplex projection (Sec. II-B; Alg. 1 phase 1);
+ *   - one table per library reused to cross-map every target series (Sec. III-B, Alg. 2)
+ *     through the lookup of Alg. 5 and a Pearson correlation (corrcoef).
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns a ccm_status.  No C++ exception crosses this boundary.
+ *   - Array arguments are DEVICE pointers owned by the caller, unless stated otherwise.
+ *     The library keeps no allocation between calls; scratch space is the caller's
+ *     workspace (size from ccm_workspace_size).
+ *   - Every call is asynchronous on `stream` (a hipStream_t passed as void*, NULL = the
+ *     default stream) and never synchronises the host.  Device-side problems that cannot
+ *     be seen without a synchronisation (a library E out of range) are reported in the
+ *     outputs, as described per function, never by blocking.
+ *   - The series panel `ts` is time-major: value x_c(t) of series c is ts[t * ld + c],
+ *     t = 0 .. L-1.  Series indices (ids) are columns of that panel.
+ *   - Time indices are int32; values are float32; correlation moments are float64.
+ *   - A point of an E-dimensional embedding is labelled by its newest coordinate:
+ *     point t = (x(t), x(t - tau), ..., x(t - (E-1) tau)), t >= (E-1) tau.
+ *   - Inputs must be finite.
+ *   - 1 <= E <= CCM_E_MAX, tau >= 1, L <= CCM_L_MAX.
+ */
+#ifndef CCM_H
+#define CCM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ccm_status;
+
+#define CCM_OK 0
+#define CCM_EINVAL 1     /* null pointer, negative size, bad enum                      */
+#define CCM_ERANGE 2     /* E outside [1, CCM_E_MAX], k > admissible candidates, L too big */
+#define CCM_EDEVICE 3    /* a HIP runtime error; text in ccm_last_error()              */
+#define CCM_ENOTSUP 4    /* valid request this build does not implement                */
+#define CCM_EWORKSPACE 5 /* workspace missing or smaller than ccm_workspace_size says  */
+
+#define CCM_E_MAX 20
+#define CCM_K_MAX (CCM_E_MAX + 1)
+#define CCM_L_MAX 16384
+
+/* selection protocol of ccm_simplex_optE */
+#define CCM_MODE_LOO 0   /* leave-one-out over the whole series (query excluded)         */
+#define CCM_MODE_HALF 1  /* the paper's split: first half = library, second half = target */
+
+/* arithmetic form of ccm_crossmap_rho */
+#define CCM_PRECISION_FP32 0 /* FP32 gather of the k neighbour rows, FP64 moments       */
+#define CCM_PRECISION_BF16 1 /* tables densified to BF16, MFMA contraction, FP32 accum.  */
+
+/* operation codes of ccm_workspace_size */
+#define CCM_OP_EMBED 0
+#define CCM_OP_KNN 1
+#define CCM_OP_SIMPLEX 2
+#define CCM_OP_CROSSMAP_FP32 3
+#define CCM_OP_CROSSMAP_BF16 4
+#define CCM_OP_CROSSMAP_BACKWARD 5
+
+/*
+ * ccm_embed -- delay embedding (Sec. II-B; the explicit blocks of Alg. 4).
+ *   ts [L][ld]       input panel.
+ *   ids [n]          series (columns of ts) to embed.
+ *   emb [n][L-(E-1)tau][E]  output; emb[i][r][e] = ts[(r + (E-1)tau - e tau) * ld + ids[i]].
+ * Errors: EINVAL for null pointers or n < 0; ERANGE if E outside [1, CCM_E_MAX], tau < 1
+ * or (E-1) tau >= L.  ids out of [0, ld) are the caller's responsibility.
+ */
+ccm_status ccm_embed(const float* ts, int64_t ld, int32_t L, const int32_t* ids, int32_t n,
+                     int32_t E, int32_t tau, float* emb, void* stream);
+
+/*
+ * ccm_knn -- neighbour tables, one per library, at the library's own E (Sec. III-B,
+ * Alg. 2 lines computing indices/distances, Alg. 3 / Alg. 4; weights per Sec. III-A).
+ *   lib_ids [n_lib]  library series (columns of ts).
+ *   lib_E   [n_lib]  embedding dimension of each library (device array).
+ *   Tp               prediction horizon; candidates s need s + Tp <= L-1.  The cross-map
+ *                    uses Tp = 0.
+ *   Query set = candidate set = {t : (E-1) tau <= t <= L-1-Tp}; a query is excluded from
+ *   its own candidates; k = E + 1 smallest by (d^2, time index) where
+ *   d^2 = canonical FP32 sum over lags e = 0..E-1 of (x(t-e tau) - x(s-e tau))^2, each
+ *   subtraction, product and sum rounded once, lag 0 first.
+ *   Outputs, row-major [n_lib][L][k_max]:
+ *     nbr_idx  neighbour time indices, nearest first;
+ *     nbr_w    weights u_k / sum(u), u_k = exp(-d_k / d_1), d = sqrt(d^2) in FP32; when
+ *              d_1 = 0, u_k = 1 where d_k = 0 and 0 elsewhere;
+ *     nbr_d2   (nullable) the FP32 d^2 of each neighbour.
+ *   Rows t outside the query set and slots beyond E + 1 are padding: idx = -1, w = 0,
+ *   d2 = +inf.  A library whose E is out of [1, CCM_E_MAX], has E + 1 > k_max, or has
+ *   fewer than E + 2 points gets padding in every row (and NaN rho downstream).
+ * Errors: EINVAL (nulls, n_lib < 0, k_max < 2 or > CCM_K_MAX, Tp < 0); ERANGE (L or tau).
+ * Workspace: none (ws may be NULL).
+ */
+ccm_status ccm_knn(const float* ts, int64_t ld, int32_t L, const int32_t* lib_ids,
+                   const int32_t* lib_E, int32_t n_lib, int32_t tau, int32_t Tp, int32_t k_max,
+                   int32_t* nbr_idx, float* nbr_w, float* nbr_d2, void* ws, size_t ws_bytes,
+                   void* stream);
+
+/*
+ * ccm_simplex_optE -- optimal embedding dimension per series by simplex projection
+ * (Sec. II-B; Alg. 1 lines "for E = 1..E_max ... optE = argmax").
+ *   For every E in [E_min, E_max]: neighbours as in ccm_knn with horizon Tp, prediction
+ *   xhat(t+Tp) = sum_k w_k x(n_k + Tp), skill rho_E = Pearson(x(t+Tp), xhat(t+Tp)) over the
+ *   query set (FP64 sums).  mode CCM_MODE_LOO: query = candidate set over the whole series,
+ *   query excluded.  mode CCM_MODE_HALF: candidates from the first half [0, L/2) and queries
+ *   from the second half, each half embedded on its own, no exclusion.
+ *   optE [n]                 smallest E reaching the largest non-NaN rho_E (E_min if all NaN).
+ *   rho_E [n][E_max-E_min+1] (nullable) the skills; NaN where a variance vanishes.
+ * Errors: EINVAL (nulls, bad mode, Tp < 0); ERANGE (E range, or too few points for
+ * k = E_max + 1 candidates).  Workspace: ccm_workspace_size(CCM_OP_SIMPLEX, ...).
+ */
+ccm_status ccm_simplex_optE(const float* ts, int64_t ld, int32_t L, const int32_t* ids,
+                            int32_t n, int32_t E_min, int32_t E_max, int32_t tau, int32_t Tp,
+                            int32_t mode, int32_t* optE, float* rho_E, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/*
+ * ccm_crossmap_rho -- cross-map every target with every library table and reduce each
+ * prediction to Pearson rho (Sec. III-B, Alg. 2 inner loop, Alg. 5, corrcoef).
+ *   nbr_idx, nbr_w [n_lib][L][k_max]  tables from ccm_knn (Tp = 0).
+ *   lib_E [n_lib]                    E of each library (device); rows t >= (E-1) tau used.
+ *   targets: series tgt0 .. tgt0 + n_tgt - 1 of ts.
+ *   yhat_ij(t) = sum_k w_i[t,k] * ts[n_ik(t) * ld + j];  rho[i][j - tgt0] = Pearson over
+ *   t = (E_i-1) tau .. L-1 of (ts[t * ld + j], yhat_ij(t)); NaN where a variance vanishes.
+ *   precision CCM_PRECISION_FP32: FP32 products and sums per prediction, FP64 moments.
+ *   precision CCM_PRECISION_BF16: target values and weights rounded to BF16, contracted on
+ *   MFMA with FP32 accumulation; observed values FP32; FP64 moments.
+ *   rho [n_lib][n_tgt]               output (row = library, column = target).
+ *   moments [n_lib][n_tgt][3]        (nullable) FP64 sum(yhat), sum(yhat^2), sum(y*yhat).
+ * Errors: EINVAL (nulls, sizes, precision), ERANGE (k_max, L), EWORKSPACE.
+ * Workspace: ccm_workspace_size(CCM_OP_CROSSMAP_FP32 or _BF16, L, n_lib, n_tgt, k_max).
+ */
+ccm_status ccm_crossmap_rho(const float* ts, int64_t ld, int32_t L, const int32_t* nbr_idx,
+                            const float* nbr_w, const int32_t* lib_E, int32_t n_lib,
+                            int32_t k_max, int32_t tau, int32_t tgt0, int32_t n_tgt,
+                            int32_t precision, float* rho, double* moments, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/*
+ * ccm_crossmap_rho_backward -- adjoint of loss = sum_p grad_rho[p] * rho[pair_lib[p]][pair_tgt[p]]
+ * with every neighbour set held fixed.
+ *   lib_ts [n_lib][L]   the library series (contiguous rows) the tables were built from.
+ *   nbr_idx, nbr_w, lib_E, k_max, tau as in ccm_crossmap_rho (Tp = 0 tables).
+ *   pair_lib [n_pairs], pair_tgt [n_pairs]  library row and target COLUMN of ts of each pair.
+ *   grad_rho [n_pairs]  upstream gradient of each pair's rho.
+ *   grad_ts [L][ld]     (nullable) += d loss / d ts through the targets (observed values and
+ *                       the looked-up neighbour values).
+ *   grad_lib [n_lib][L] (nullable) += d loss / d library series through the weights
+ *                       (distances -> exp -> normalisation, including the d_1 path).
+ *   The gradient through a zero distance (d_k = 0 or d_1 = 0) is taken as 0.  Pairs whose
+ *   rho is NaN contribute nothing.  Accumulation order is fixed (no atomics), so results
+ *   are deterministic.
+ * Errors: EINVAL, ERANGE, EWORKSPACE.  Workspace: CCM_OP_CROSSMAP_BACKWARD.
+ */
+ccm_status ccm_crossmap_rho_backward(const float* ts, int64_t ld, int32_t L, const float* lib_ts,
+                                     const int32_t* nbr_idx, const float* nbr_w,
+                                     const int32_t* lib_E, int32_t n_lib, int32_t k_max,
+                                     int32_t tau, const int32_t* pair_lib,
+                                     const int32_t* pair_tgt, const float* grad_rho,
+                                     int32_t n_pairs, float* grad_ts, float* grad_lib, void* ws,
+                                     size_t ws_bytes, void* stream);
+
+/*
+ * ccm_workspace_size -- bytes of workspace the operation `op` needs (host call, no device
+ * work).  n_tgt is the number of targets (crossmap) or of pairs (backward).
+ */
+ccm_status ccm_workspace_size(int32_t op, int32_t L, int32_t n_lib, int32_t n_tgt,
+                              int32_t k_max, size_t* bytes);
+
+/* Static text of a status code. */
+const char* ccm_status_string(ccm_status s);
+/* Text of the last error raised on the calling thread ("" if none). */
+const char* ccm_last_error(void);
+/* Library version string. */
+const char* ccm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CCM_H */

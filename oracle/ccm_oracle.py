@@ -31,7 +31,7 @@ design notes):
     u_k = exp(-d_k / d_1), w_k = u_k / sum(u); when d_1 = 0, u_k = 1 where d_k = 0 and 0
     elsewhere (the limit d_1 -> 0+);
   * everything after the selection is FP64; Pearson is the two-pass centred formula and is
-    NaN when either centred sum of squares is zero;
+    NaN when either centred sum of squares vanishes (<= 1e-10 of the raw sum of squares);
   * optE is scored by leave-one-out simplex at Tp = 1 (query = candidate set, self
     excluded); the paper's half split is kept as ``mode = HALF``; the smallest E reaching
     the largest non-NaN rho wins;
@@ -176,7 +176,11 @@ def weights_rows_fp64(x, Q, idx, E: int, tau: int) -> np.ndarray:
 
 
 def pearson(a, b) -> float:
-    """Two-pass centred Pearson correlation in FP64; NaN if either variance is zero."""
+    """Two-pass centred Pearson correlation in FP64.
+
+    NaN if either centred sum of squares vanishes, read as: is at most 1e-10 of the raw
+    sum of squares (a variance below the rounding level of the data is indistinguishable
+    from zero; an exactly constant series always lands here)."""
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     if a.size == 0:
@@ -185,7 +189,7 @@ def pearson(a, b) -> float:
     db = b - b.mean()
     saa = float(np.sum(da * da))
     sbb = float(np.sum(db * db))
-    if saa == 0.0 or sbb == 0.0:
+    if saa <= 1e-10 * float(np.sum(a * a)) or sbb <= 1e-10 * float(np.sum(b * b)):
         return float("nan")
     return float(np.sum(da * db) / np.sqrt(saa * sbb))
 

@@ -1,0 +1,234 @@
+"""MI355X (gfx950) all-pairs Convergent Cross Mapping hot path.
+
+Thin ctypes binding over the C ABI of ``libccm.so`` (declared in include/ccm.h).  It only
+marshals arguments: tensors become device pointers, the current torch stream becomes the
+HIP stream, and a caller-owned workspace is allocated through torch's caching allocator.
+Every step of the computation runs in the library's HIP kernels; there is no fallback.
+
+Entry points (same names as the C ABI, minus the ``ccm_`` prefix):
+  embed, knn, simplex_optE, crossmap_rho, crossmap_rho_backward, workspace_size
+and the differentiable wrapper ``CrossMapRho`` / ``crossmap_rho_autograd``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch  # loaded first: the library then binds to torch's HIP runtime
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libccm.so")
+
+CCM_OK, CCM_EINVAL, CCM_ERANGE, CCM_EDEVICE, CCM_ENOTSUP, CCM_EWORKSPACE = range(6)
+E_MAX = 20
+K_MAX = 21
+MODE_LOO, MODE_HALF = 0, 1
+PRECISION_FP32, PRECISION_BF16 = 0, 1
+OP_EMBED, OP_KNN, OP_SIMPLEX, OP_CROSSMAP_FP32, OP_CROSSMAP_BF16, OP_CROSSMAP_BACKWARD = range(6)
+
+EXPORTED = (
+    "ccm_embed", "ccm_knn", "ccm_simplex_optE", "ccm_crossmap_rho", "ccm_crossmap_rho_backward",
+    "ccm_workspace_size", "ccm_status_string", "ccm_last_error", "ccm_version",
+)
+
+
+class CCMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[status {status}] {msg}")
+        self.status = status
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
+
+
+def load_library(path: Optional[str] = None) -> ctypes.CDLL:
+    """Load libccm.so (raises if it has not been built: there is no fallback path)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with __graft_entry__.build() "
+                           "(the CCM kernels have no CPU fallback)")
+    lib = ctypes.CDLL(p)
+    sig = {
+        "ccm_embed": [_P, _I64, _I32, _P, _I32, _I32, _I32, _P, _P],
+        "ccm_knn": [_P, _I64, _I32, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _SZ, _P],
+        "ccm_simplex_optE": [_P, _I64, _I32, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P,
+                             _SZ, _P],
+        "ccm_crossmap_rho": [_P, _I64, _I32, _P, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P,
+                             _P, _P, _SZ, _P],
+        "ccm_crossmap_rho_backward": [_P, _I64, _I32, _P, _P, _P, _P, _I32, _I32, _I32, _P, _P,
+                                      _P, _I32, _P, _P, _P, _SZ, _P],
+        "ccm_workspace_size": [_I32, _I32, _I32, _I32, _I32, ctypes.POINTER(_SZ)],
+        "ccm_status_string": [_I32],
+        "ccm_last_error": [],
+        "ccm_version": [],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_char_p if name in ("ccm_status_string", "ccm_last_error",
+                                                "ccm_version") else _I32
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != CCM_OK:
+        lib = load_library()
+        raise CCMError(status, (lib.ccm_last_error() or b"").decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str, dtype=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return t
+
+
+def _panel(ts: torch.Tensor):
+    """(tensor, ld, L) of a time-major [L][N] float32 panel with unit column stride."""
+    _dev(ts, "ts", torch.float32)
+    if ts.dim() != 2 or ts.stride(1) != 1:
+        raise ValueError("ts must be a 2-D [L][N] panel with unit stride along N")
+    return ts, int(ts.stride(0)), int(ts.shape[0])
+
+
+def _i32(t, device) -> torch.Tensor:
+    if isinstance(t, torch.Tensor):
+        t = t.to(device=device, dtype=torch.int32)
+    else:
+        t = torch.as_tensor(t, dtype=torch.int32, device=device)
+    return t.contiguous()
+
+
+def workspace_size(op: int, L: int, n_lib: int, n_tgt: int, k_max: int) -> int:
+    lib = load_library()
+    out = _SZ(0)
+    _check(lib.ccm_workspace_size(op, L, n_lib, n_tgt, k_max, ctypes.byref(out)))
+    return int(out.value)
+
+
+def _workspace(op, L, n_lib, n_tgt, k_max, device, ws=None):
+    need = workspace_size(op, L, n_lib, n_tgt, k_max)
+    if ws is not None:
+        return ws, need
+    if need == 0:
+        return None, 0
+    return torch.empty(need, dtype=torch.uint8, device=device), need
+
+
+def embed(ts: torch.Tensor, ids, E: int, tau: int = 1) -> torch.Tensor:
+    """Delay embedding [n][L-(E-1)tau][E] of series ``ids`` (columns of ts)."""
+    lib = load_library()
+    ts, ld, L = _panel(ts)
+    ids = _i32(ids, ts.device)
+    n = ids.numel()
+    emb = torch.empty((n, max(L - (E - 1) * tau, 0), E), dtype=torch.float32, device=ts.device)
+    _check(lib.ccm_embed(_ptr(ts), ld, L, _ptr(ids), n, E, tau, _ptr(emb), _stream()))
+    return emb
+
+
+def knn(ts: torch.Tensor, lib_ids, lib_E, tau: int = 1, Tp: int = 0, k_max: int = K_MAX,
+        want_d2: bool = True):
+    """Neighbour tables (idx int32, w float32, d2 float32 or None), each [n_lib][L][k_max]."""
+    lib = load_library()
+    ts, ld, L = _panel(ts)
+    lib_ids = _i32(lib_ids, ts.device)
+    lib_E = _i32(lib_E, ts.device)
+    n = lib_ids.numel()
+    if lib_E.numel() != n:
+        raise ValueError("lib_E and lib_ids differ in length")
+    idx = torch.empty((n, L, k_max), dtype=torch.int32, device=ts.device)
+    w = torch.empty((n, L, k_max), dtype=torch.float32, device=ts.device)
+    d2 = torch.empty((n, L, k_max), dtype=torch.float32, device=ts.device) if want_d2 else None
+    _check(lib.ccm_knn(_ptr(ts), ld, L, _ptr(lib_ids), _ptr(lib_E), n, tau, Tp, k_max, _ptr(idx),
+                       _ptr(w), _ptr(d2), None, 0, _stream()))
+    return idx, w, d2
+
+
+def simplex_optE(ts: torch.Tensor, ids, E_min: int = 1, E_max: int = E_MAX, tau: int = 1,
+                 Tp: int = 1, mode: int = MODE_LOO):
+    """(optE int32 [n], rho_E float32 [n][E_max-E_min+1])."""
+    lib = load_library()
+    ts, ld, L = _panel(ts)
+    ids = _i32(ids, ts.device)
+    n = ids.numel()
+    optE = torch.empty(n, dtype=torch.int32, device=ts.device)
+    rho_E = torch.empty((n, E_max - E_min + 1), dtype=torch.float32, device=ts.device)
+    ws, need = _workspace(OP_SIMPLEX, L, n, 0, 0, ts.device)
+    _check(lib.ccm_simplex_optE(_ptr(ts), ld, L, _ptr(ids), n, E_min, E_max, tau, Tp, mode,
+                                _ptr(optE), _ptr(rho_E), _ptr(ws), need, _stream()))
+    return optE, rho_E
+
+
+def crossmap_rho(ts: torch.Tensor, nbr_idx: torch.Tensor, nbr_w: torch.Tensor, lib_E,
+                 tau: int = 1, tgt0: int = 0, n_tgt: Optional[int] = None,
+                 precision: int = PRECISION_FP32, want_moments: bool = False,
+                 ws: Optional[torch.Tensor] = None):
+    """rho [n_lib][n_tgt] (and FP64 moments [n_lib][n_tgt][3] if asked)."""
+    lib = load_library()
+    ts, ld, L = _panel(ts)
+    _dev(nbr_idx, "nbr_idx", torch.int32)
+    _dev(nbr_w, "nbr_w", torch.float32)
+    if not (nbr_idx.is_contiguous() and nbr_w.is_contiguous()):
+        raise ValueError("tables must be contiguous")
+    n_lib, L2, k_max = nbr_idx.shape
+    if L2 != L or nbr_w.shape != nbr_idx.shape:
+        raise ValueError("table shape does not match the panel")
+    lib_E = _i32(lib_E, ts.device)
+    if n_tgt is None:
+        n_tgt = int(ts.shape[1]) - tgt0
+    rho = torch.empty((n_lib, n_tgt), dtype=torch.float32, device=ts.device)
+    mom = (torch.empty((n_lib, n_tgt, 3), dtype=torch.float64, device=ts.device)
+           if want_moments else None)
+    op = OP_CROSSMAP_FP32 if precision == PRECISION_FP32 else OP_CROSSMAP_BF16
+    ws, need = _workspace(op, L, n_lib, n_tgt, k_max, ts.device, ws)
+    nbytes = ws.numel() if ws is not None else 0
+    _check(lib.ccm_crossmap_rho(_ptr(ts), ld, L, _ptr(nbr_idx), _ptr(nbr_w), _ptr(lib_E), n_lib,
+                                k_max, tau, tgt0, n_tgt, precision, _ptr(rho), _ptr(mom), _ptr(ws),
+                                nbytes, _stream()))
+    return (rho, mom) if want_moments else rho
+
+
+def crossmap_rho_backward(ts, lib_ts, nbr_idx, nbr_w, lib_E, pair_lib, pair_tgt, grad_rho,
+                          tau: int = 1, grad_ts=None, grad_lib=None):
+    """Adjoint of sum_p grad_rho[p] * rho[pair_lib[p], pair_tgt[p]] with fixed neighbour sets.
+
+    Accumulates into (and returns) grad_ts [L][ld] and grad_lib [n_lib][L] (float32)."""
+    lib = load_library()
+    ts, ld, L = _panel(ts)
+    n_lib, _, k_max = nbr_idx.shape
+    lib_E = _i32(lib_E, ts.device)
+    pair_lib = _i32(pair_lib, ts.device)
+    pair_tgt = _i32(pair_tgt, ts.device)
+    grad_rho = grad_rho.to(device=ts.device, dtype=torch.float32).contiguous()
+    n_pairs = pair_lib.numel()
+    if grad_ts is None:
+        grad_ts = torch.zeros((L, ld), dtype=torch.float32, device=ts.device)
+    if grad_lib is None:
+        grad_lib = torch.zeros((n_lib, L), dtype=torch.float32, device=ts.device)
+    lib_ts = lib_ts.to(torch.float32).contiguous()
+    ws, need = _workspace(OP_CROSSMAP_BACKWARD, L, n_lib, n_pairs, k_max, ts.device)
+    _check(lib.ccm_crossmap_rho_backward(_ptr(ts), ld, L, _ptr(lib_ts), _ptr(nbr_idx), _ptr(nbr_w),
+                                         _ptr(lib_E), n_lib, k_max, tau, _ptr(pair_lib),
+                                         _ptr(pair_tgt), _ptr(grad_rho), n_pairs, _ptr(grad_ts),
+                                         _ptr(grad_lib), _ptr(ws), need, _stream()))
+    return grad_ts, grad_lib

@@ -1,0 +1,215 @@
+// C ABI of the CCM hot path: argument checks, workspace layout and kernel launches.
+// Every entry point is asynchronous on the caller's stream and never synchronises.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/ccm.h"
+
+extern "C" {
+hipError_t ccm_launch_knn(const float* ts, int64_t ld, int L, const int* lib_ids, const int* lib_E,
+                          int n_lib, int tau, int Tp, int k_max, int* nbr_idx, float* nbr_w,
+                          float* nbr_d2, hipStream_t stream);
+hipError_t ccm_launch_simplex(const float* ts, int64_t ld, int L, const int* ids, int n, int E_min,
+                              int E_max, int tau, int Tp, int mode, int* optE, float* rho_E,
+                              hipStream_t stream);
+hipError_t ccm_launch_embed(const float* ts, int64_t ld, int L, const int* ids, int n, int E,
+                            int tau, float* emb, hipStream_t stream);
+size_t ccm_gather_lds_bytes(int L);
+hipError_t ccm_launch_crossmap_fp32(const float* ts, int64_t ld, int L, int tau, int tgt0,
+                                    int n_tgt, const int* nbr_idx, const float* nbr_w,
+                                    const int* lib_E, int n_lib, int k_max, float* rho,
+                                    double* moments, uint32_t* poff, float* pw, int* lib_k,
+                                    int* order, hipStream_t stream);
+}
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ccm_status fail(ccm_status s, const char* fn, const char* msg) {
+  g_last_error = std::string(fn) + ": " + msg;
+  return s;
+}
+
+ccm_status device_status(const char* fn, hipError_t e) {
+  if (e == hipSuccess) return CCM_OK;
+  g_last_error = std::string(fn) + ": HIP error: " + hipGetErrorString(e);
+  return CCM_EDEVICE;
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Workspace of the FP32 cross-map: blocked tables (byte offsets, weights), lib_k, order.
+struct CrossmapWs {
+  size_t off_poff, off_pw, off_libk, off_order, total;
+};
+
+CrossmapWs crossmap_ws(int L, int n_lib, int k_max) {
+  CrossmapWs w;
+  const size_t nblk = (size_t)(L + 15) / 16;
+  const size_t KSM = (size_t)(k_max + 3) / 4;
+  const size_t ent = (size_t)n_lib * nblk * KSM * 64;
+  w.off_poff = 0;
+  w.off_pw = align_up(w.off_poff + ent * 4);
+  w.off_libk = align_up(w.off_pw + ent * 4);
+  w.off_order = align_up(w.off_libk + (size_t)n_lib * 4);
+  w.total = align_up(w.off_order + (size_t)n_lib * 4);
+  return w;
+}
+
+bool check_series(const char* fn, ccm_status* st, const float* ts, int64_t ld, int32_t L,
+                  int32_t tau) {
+  if (!ts) { *st = fail(CCM_EINVAL, fn, "ts is NULL"); return false; }
+  if (ld < 1) { *st = fail(CCM_EINVAL, fn, "ld must be >= 1"); return false; }
+  if (L < 2 || L > CCM_L_MAX) { *st = fail(CCM_ERANGE, fn, "L outside [2, CCM_L_MAX]"); return false; }
+  if (tau < 1) { *st = fail(CCM_ERANGE, fn, "tau must be >= 1"); return false; }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ccm_version(void) { return "ccm-gfx950 0.1"; }
+
+const char* ccm_last_error(void) { return g_last_error.c_str(); }
+
+const char* ccm_status_string(ccm_status s) {
+  switch (s) {
+    case CCM_OK: return "CCM_OK";
+    case CCM_EINVAL: return "CCM_EINVAL: invalid argument";
+    case CCM_ERANGE: return "CCM_ERANGE: value out of range";
+    case CCM_EDEVICE: return "CCM_EDEVICE: HIP runtime error";
+    case CCM_ENOTSUP: return "CCM_ENOTSUP: not supported";
+    case CCM_EWORKSPACE: return "CCM_EWORKSPACE: workspace too small";
+    default: return "unknown ccm_status";
+  }
+}
+
+ccm_status ccm_workspace_size(int32_t op, int32_t L, int32_t n_lib, int32_t n_tgt, int32_t k_max,
+                              size_t* bytes) {
+  if (!bytes) return fail(CCM_EINVAL, "ccm_workspace_size", "bytes is NULL");
+  if (L < 0 || n_lib < 0 || n_tgt < 0 || k_max < 0)
+    return fail(CCM_EINVAL, "ccm_workspace_size", "negative size");
+  switch (op) {
+    case CCM_OP_EMBED:
+    case CCM_OP_KNN:
+    case CCM_OP_SIMPLEX:
+      *bytes = 0;
+      return CCM_OK;
+    case CCM_OP_CROSSMAP_FP32:
+      *bytes = crossmap_ws(L, n_lib, k_max).total;
+      return CCM_OK;
+    case CCM_OP_CROSSMAP_BF16:
+    case CCM_OP_CROSSMAP_BACKWARD:
+      *bytes = 0;
+      return CCM_OK;
+    default:
+      return fail(CCM_EINVAL, "ccm_workspace_size", "unknown op");
+  }
+}
+
+ccm_status ccm_embed(const float* ts, int64_t ld, int32_t L, const int32_t* ids, int32_t n,
+                     int32_t E, int32_t tau, float* emb, void* stream) {
+  const char* fn = "ccm_embed";
+  ccm_status st = CCM_OK;
+  if (!check_series(fn, &st, ts, ld, L, tau)) return st;
+  if (n < 0) return fail(CCM_EINVAL, fn, "n < 0");
+  if (n > 0 && (!ids || !emb)) return fail(CCM_EINVAL, fn, "ids or emb is NULL");
+  if (E < 1 || E > CCM_E_MAX) return fail(CCM_ERANGE, fn, "E outside [1, CCM_E_MAX]");
+  if ((int64_t)(E - 1) * tau >= L) return fail(CCM_ERANGE, fn, "(E-1)*tau >= L");
+  return device_status(fn, ccm_launch_embed(ts, ld, L, ids, n, E, tau, emb, (hipStream_t)stream));
+}
+
+ccm_status ccm_knn(const float* ts, int64_t ld, int32_t L, const int32_t* lib_ids,
+                   const int32_t* lib_E, int32_t n_lib, int32_t tau, int32_t Tp, int32_t k_max,
+                   int32_t* nbr_idx, float* nbr_w, float* nbr_d2, void* ws, size_t ws_bytes,
+                   void* stream) {
+  (void)ws;
+  (void)ws_bytes;
+  const char* fn = "ccm_knn";
+  ccm_status st = CCM_OK;
+  if (!check_series(fn, &st, ts, ld, L, tau)) return st;
+  if (n_lib < 0) return fail(CCM_EINVAL, fn, "n_lib < 0");
+  if (n_lib > 0 && (!lib_ids || !lib_E || !nbr_idx || !nbr_w))
+    return fail(CCM_EINVAL, fn, "NULL array argument");
+  if (k_max < 2 || k_max > CCM_K_MAX) return fail(CCM_EINVAL, fn, "k_max outside [2, CCM_K_MAX]");
+  if (Tp < 0 || Tp >= L) return fail(CCM_EINVAL, fn, "Tp outside [0, L)");
+  return device_status(fn, ccm_launch_knn(ts, ld, L, lib_ids, lib_E, n_lib, tau, Tp, k_max, nbr_idx,
+                                          nbr_w, nbr_d2, (hipStream_t)stream));
+}
+
+ccm_status ccm_simplex_optE(const float* ts, int64_t ld, int32_t L, const int32_t* ids, int32_t n,
+                            int32_t E_min, int32_t E_max, int32_t tau, int32_t Tp, int32_t mode,
+                            int32_t* optE, float* rho_E, void* ws, size_t ws_bytes, void* stream) {
+  (void)ws;
+  (void)ws_bytes;
+  const char* fn = "ccm_simplex_optE";
+  ccm_status st = CCM_OK;
+  if (!check_series(fn, &st, ts, ld, L, tau)) return st;
+  if (n < 0) return fail(CCM_EINVAL, fn, "n < 0");
+  if (n > 0 && (!ids || !optE)) return fail(CCM_EINVAL, fn, "ids or optE is NULL");
+  if (mode != CCM_MODE_LOO && mode != CCM_MODE_HALF) return fail(CCM_EINVAL, fn, "unknown mode");
+  if (Tp < 0) return fail(CCM_EINVAL, fn, "Tp < 0");
+  if (E_min < 1 || E_max > CCM_E_MAX || E_min > E_max)
+    return fail(CCM_ERANGE, fn, "need 1 <= E_min <= E_max <= CCM_E_MAX");
+  // admissible candidates at the largest E must cover k = E_max + 1
+  const int64_t lo = (int64_t)(E_max - 1) * tau;
+  int64_t ncand;
+  if (mode == CCM_MODE_LOO)
+    ncand = (L - 1 - Tp) - lo + 1 - 1;  // query excluded
+  else
+    ncand = (L / 2 - 1 - Tp) - lo + 1;
+  if (ncand < E_max + 1) return fail(CCM_ERANGE, fn, "too few points for k = E_max + 1 neighbours");
+  return device_status(fn, ccm_launch_simplex(ts, ld, L, ids, n, E_min, E_max, tau, Tp, mode, optE,
+                                              rho_E, (hipStream_t)stream));
+}
+
+ccm_status ccm_crossmap_rho(const float* ts, int64_t ld, int32_t L, const int32_t* nbr_idx,
+                            const float* nbr_w, const int32_t* lib_E, int32_t n_lib, int32_t k_max,
+                            int32_t tau, int32_t tgt0, int32_t n_tgt, int32_t precision, float* rho,
+                            double* moments, void* ws, size_t ws_bytes, void* stream) {
+  const char* fn = "ccm_crossmap_rho";
+  ccm_status st = CCM_OK;
+  if (!check_series(fn, &st, ts, ld, L, tau)) return st;
+  if (n_lib < 0 || n_tgt < 0 || tgt0 < 0) return fail(CCM_EINVAL, fn, "negative size or offset");
+  if ((int64_t)tgt0 + n_tgt > ld) return fail(CCM_EINVAL, fn, "targets exceed the panel width ld");
+  if (n_lib > 0 && n_tgt > 0 && (!nbr_idx || !nbr_w || !lib_E || !rho))
+    return fail(CCM_EINVAL, fn, "NULL array argument");
+  if (k_max < 2 || k_max > CCM_K_MAX) return fail(CCM_EINVAL, fn, "k_max outside [2, CCM_K_MAX]");
+  if (L < 4) return fail(CCM_ERANGE, fn, "L < 4");
+  if (precision == CCM_PRECISION_FP32) {
+    if (ccm_gather_lds_bytes(L) > 160 * 1024)
+      return fail(CCM_ENOTSUP, fn, "L too large for the 16-target LDS tile (max 2475)");
+    CrossmapWs w = crossmap_ws(L, n_lib, k_max);
+    if (n_lib == 0 || n_tgt == 0) return CCM_OK;
+    if (!ws || ws_bytes < w.total) return fail(CCM_EWORKSPACE, fn, "workspace too small");
+    char* base = (char*)ws;
+    return device_status(
+        fn, ccm_launch_crossmap_fp32(ts, ld, L, tau, tgt0, n_tgt, nbr_idx, nbr_w, lib_E, n_lib, k_max,
+                                     rho, moments, (uint32_t*)(base + w.off_poff),
+                                     (float*)(base + w.off_pw), (int*)(base + w.off_libk),
+                                     (int*)(base + w.off_order), (hipStream_t)stream));
+  }
+  if (precision == CCM_PRECISION_BF16) return fail(CCM_ENOTSUP, fn, "BF16 form not built yet");
+  return fail(CCM_EINVAL, fn, "unknown precision");
+}
+
+ccm_status ccm_crossmap_rho_backward(const float* ts, int64_t ld, int32_t L, const float* lib_ts,
+                                     const int32_t* nbr_idx, const float* nbr_w,
+                                     const int32_t* lib_E, int32_t n_lib, int32_t k_max,
+                                     int32_t tau, const int32_t* pair_lib, const int32_t* pair_tgt,
+                                     const float* grad_rho, int32_t n_pairs, float* grad_ts,
+                                     float* grad_lib, void* ws, size_t ws_bytes, void* stream) {
+  (void)ts; (void)ld; (void)L; (void)lib_ts; (void)nbr_idx; (void)nbr_w; (void)lib_E; (void)n_lib;
+  (void)k_max; (void)tau; (void)pair_lib; (void)pair_tgt; (void)grad_rho; (void)n_pairs;
+  (void)grad_ts; (void)grad_lib; (void)ws; (void)ws_bytes; (void)stream;
+  return fail(CCM_ENOTSUP, "ccm_crossmap_rho_backward", "not built yet");
+}
+
+}  // extern "C"

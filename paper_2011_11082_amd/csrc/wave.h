@@ -1,0 +1,63 @@
+// Wavefront-level helpers for gfx950 (64-lane waves).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ccm {
+
+constexpr int kWave = 64;
+constexpr int kEMax = 20;
+constexpr int kKMax = kEMax + 1;
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ float readlane(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ int readlane(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+// DPP wave_shr:1 -- lane i receives lane i-1; lane 0 keeps `old`.
+__device__ __forceinline__ float wave_shr1(float v, float old) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ int wave_shr1(int v, int old) {
+  return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xF, 0xF, false);
+}
+
+// DPP quad_perm broadcast: every lane of a quad receives lane M of that quad.
+template <int M>
+__device__ __forceinline__ int quad_bcast(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, M * 0x55, 0xF, 0xF, false);
+}
+template <int M>
+__device__ __forceinline__ float quad_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), M * 0x55, 0xF, 0xF, false));
+}
+
+// Sum over all 64 lanes (result in every lane).
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Pearson correlation from one-pass FP64 moments of n pairs (y, p).  A variance below the
+// rounding level of the data (relative 1e-10 of the raw second moment) counts as zero and
+// gives NaN.
+__device__ __forceinline__ double pearson_from_moments(double n, double sy, double syy, double sp,
+                                                       double spp, double syp) {
+  double vy = n * syy - sy * sy;
+  double vp = n * spp - sp * sp;
+  if (!(vy > 1e-10 * n * syy) || !(vp > 1e-10 * n * spp)) return __builtin_nan("");
+  return (n * syp - sy * sp) / sqrt(vy * vp);
+}
+
+}  // namespace ccm

@@ -1,0 +1,90 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared symbol, and
+rejects bad arguments before any device work (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2011_11082_amd as ccm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ccm.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(ccm.LIB_PATH), reason="libccm.so not built")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:ccm_status|const char\*)\s+(ccm_\w+)\(", text, re.M)))
+
+
+def test_header_declares_the_abi():
+    syms = declared_symbols()
+    for name in ("ccm_embed", "ccm_knn", "ccm_simplex_optE", "ccm_crossmap_rho",
+                 "ccm_crossmap_rho_backward", "ccm_workspace_size"):
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(ccm.LIB_PATH)
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    assert set(declared_symbols()) <= set(ccm.EXPORTED)
+
+
+def test_status_strings_and_version():
+    lib = ccm.load_library()
+    assert lib.ccm_status_string(0) == b"CCM_OK"
+    assert b"workspace" in lib.ccm_status_string(5)
+    assert lib.ccm_version().startswith(b"ccm-gfx950")
+
+
+def test_workspace_size_host_only():
+    n = ccm.workspace_size(ccm.OP_CROSSMAP_FP32, 1600, 512, 101729, 21)
+    # blocked tables: 512 libraries x 100 blocks x 6 slots x 64 lanes x (4 + 4) bytes
+    assert n >= 512 * 100 * 6 * 64 * 8
+    assert ccm.workspace_size(ccm.OP_KNN, 1600, 512, 0, 21) == 0
+    with pytest.raises(ccm.CCMError) as e:
+        ccm.workspace_size(99, 10, 1, 1, 2)
+    assert e.value.status == ccm.CCM_EINVAL
+
+
+def _null():
+    return ctypes.c_void_p(0)
+
+
+def test_argument_errors_return_status_before_device_work():
+    lib = ccm.load_library()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation
+    # NULL panel
+    assert lib.ccm_knn(_null(), 8, 100, fake, fake, 1, 1, 0, 21, fake, fake, _null(), _null(), 0,
+                       _null()) == ccm.CCM_EINVAL
+    assert b"ts is NULL" in lib.ccm_last_error()
+    # k_max out of range
+    assert lib.ccm_knn(fake, 8, 100, fake, fake, 1, 1, 0, 22, fake, fake, _null(), _null(), 0,
+                       _null()) == ccm.CCM_EINVAL
+    # E range of simplex
+    assert lib.ccm_simplex_optE(fake, 8, 100, fake, 1, 0, 5, 1, 1, 0, fake, _null(), _null(), 0,
+                                _null()) == ccm.CCM_ERANGE
+    assert lib.ccm_simplex_optE(fake, 8, 100, fake, 1, 1, 21, 1, 1, 0, fake, _null(), _null(), 0,
+                                _null()) == ccm.CCM_ERANGE
+    # too few points for E_max
+    assert lib.ccm_simplex_optE(fake, 8, 20, fake, 1, 1, 20, 1, 1, 0, fake, _null(), _null(), 0,
+                                _null()) == ccm.CCM_ERANGE
+    # bad mode
+    assert lib.ccm_simplex_optE(fake, 8, 100, fake, 1, 1, 5, 1, 1, 7, fake, _null(), _null(), 0,
+                                _null()) == ccm.CCM_EINVAL
+    # tau < 1, L too large
+    assert lib.ccm_embed(fake, 8, 100, fake, 1, 2, 0, fake, _null()) == ccm.CCM_ERANGE
+    assert lib.ccm_embed(fake, 8, 20000, fake, 1, 2, 1, fake, _null()) == ccm.CCM_ERANGE
+    # crossmap: workspace missing, targets past the panel, unknown precision
+    assert lib.ccm_crossmap_rho(fake, 64, 100, fake, fake, fake, 4, 21, 1, 0, 64, 0, fake, _null(),
+                                _null(), 0, _null()) == ccm.CCM_EWORKSPACE
+    assert lib.ccm_crossmap_rho(fake, 64, 100, fake, fake, fake, 4, 21, 1, 10, 64, 0, fake,
+                                _null(), _null(), 0, _null()) == ccm.CCM_EINVAL
+    assert lib.ccm_crossmap_rho(fake, 64, 100, fake, fake, fake, 4, 21, 1, 0, 64, 9, fake, _null(),
+                                _null(), 0, _null()) == ccm.CCM_EINVAL
+    # L beyond the FP32 tile
+    assert lib.ccm_crossmap_rho(fake, 64, 4000, fake, fake, fake, 4, 21, 1, 0, 64, 0, fake,
+                                _null(), _null(), 0, _null()) == ccm.CCM_ENOTSUP

@@ -1,0 +1,211 @@
+"""GPU-vs-oracle parity of the HIP path, called through the C ABI.
+
+kNN indices (and canonical FP32 d^2) must be bit-identical to the oracle's; rho must be
+within 1e-5 of the FP64 oracle using the same neighbour sets; optE must agree except where
+the oracle's two best skills are closer than 1e-6 (listed)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+RHO_TOL = 1e-5
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ccm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2011_11082_amd as m
+
+    m.load_library()
+    return m
+
+
+def _cuda(a):
+    import torch
+
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+def _check_tables(ts, lib_ids, lib_E, tau, Tp, k_max, idx_g, w_g, d2_g, label):
+    idx_o, w_o, d2_o = O.knn(ts, lib_ids, lib_E, tau, Tp, k_max)
+    bad = np.argwhere(idx_g != idx_o)
+    assert bad.size == 0, f"{label}: {len(bad)} index mismatches, first {bad[:3].tolist()}"
+    valid = idx_o >= 0
+    assert np.array_equal(d2_g[valid], d2_o[valid]), f"{label}: d2 not bit-identical"
+    assert np.all(np.isinf(d2_g[~valid])) and np.all(w_g[~valid] == 0)
+    err = np.abs(w_g.astype(np.float64) - w_o)
+    assert err.max() < 2e-6, f"{label}: weight error {err.max()}"
+
+
+# ---------------------------------------------------------------------------------------
+def test_knn_bit_exact_adversarial(ccm):
+    rng = np.random.default_rng(123)
+    L = 150
+    cols = [
+        rng.integers(0, 4, size=L).astype(np.float32),            # many exact ties
+        np.repeat(rng.integers(-3, 4, size=L // 5), 5)[:L].astype(np.float32),  # runs
+        synth.periodic(6, L, rng),                                # exact repeats, d1 = 0
+        (rng.standard_normal(L) * 1e-30).astype(np.float32),     # tiny values (subnormal d^2)
+        rng.standard_normal(L).astype(np.float32),
+        np.round(rng.standard_normal(L), 1).astype(np.float32),
+    ]
+    ts = np.stack(cols, axis=1)
+    for tau in (1, 2):
+        for Tp in (0, 1):
+            lib_ids = np.array([0, 1, 2, 3, 4, 5, 0, 4, 2], dtype=np.int32)
+            lib_E = np.array([1, 2, 3, 4, 5, 7, 6, 20, 2], dtype=np.int32)
+            _say("knn adversarial", tau, Tp)
+            idx, w, d2 = ccm.knn(_cuda(ts), lib_ids, lib_E, tau=tau, Tp=Tp, k_max=21)
+            _check_tables(ts, lib_ids, lib_E, tau, Tp, 21, idx.cpu().numpy(), w.cpu().numpy(),
+                          d2.cpu().numpy(), f"adv tau={tau} Tp={Tp}")
+
+
+def test_knn_invalid_library_gets_padding(ccm):
+    rng = np.random.default_rng(5)
+    ts = rng.standard_normal((30, 2)).astype(np.float32)
+    _say("knn invalid E")
+    idx, w, d2 = ccm.knn(_cuda(ts), [0, 1, 0], [0, 25, 20], k_max=21)
+    # E = 0, E = 25: out of range; E = 20 on 30 points leaves 10 points < k + 1 = 22
+    assert np.all(idx.cpu().numpy() == -1) and np.all(w.cpu().numpy() == 0)
+
+
+def test_knn_bit_exact_logistic64(ccm):
+    w = synth.make("logistic64")
+    ts = w.panel
+    lib_E = (np.arange(64) % 10 + 1).astype(np.int32)
+    _say("knn logistic64 all libraries, E = 1..10 mixed")
+    idx, wt, d2 = ccm.knn(_cuda(ts), np.arange(64), lib_E, k_max=11)
+    _check_tables(ts, np.arange(64), lib_E, 1, 0, 11, idx.cpu().numpy(), wt.cpu().numpy(),
+                  d2.cpu().numpy(), "logistic64")
+
+
+def test_knn_bit_exact_ratenet_sample(ccm):
+    w = synth.make("ratenet1024")
+    ts = w.panel
+    lib_ids = np.arange(0, 1024, 97, dtype=np.int32)  # 11 libraries
+    lib_E = np.array([20, 1, 2, 5, 9, 13, 17, 19, 3, 7, 11], dtype=np.int32)
+    _say("knn ratenet1024 sample")
+    idx, wt, d2 = ccm.knn(_cuda(ts), lib_ids, lib_E, k_max=21)
+    _check_tables(ts, lib_ids, lib_E, 1, 0, 21, idx.cpu().numpy(), wt.cpu().numpy(),
+                  d2.cpu().numpy(), "ratenet1024")
+
+
+# ---------------------------------------------------------------------------------------
+def _check_optE(optE_g, rho_g, optE_o, rho_o, label):
+    rho_o = np.asarray(rho_o)
+    err = np.nanmax(np.abs(rho_g.astype(np.float64) - rho_o))
+    assert np.array_equal(np.isnan(rho_g), np.isnan(rho_o)), label
+    assert err < RHO_TOL, f"{label}: rho_E error {err}"
+    near = []
+    for i in range(len(optE_o)):
+        if optE_g[i] != optE_o[i]:
+            r = np.sort(rho_o[i][~np.isnan(rho_o[i])])[::-1]
+            assert len(r) > 1 and r[0] - r[1] < 1e-6, f"{label}: optE differs at series {i}"
+            near.append(i)
+    if near:
+        print(f"{label}: optE near-ties {near}")
+
+
+def test_optE_logistic64(ccm):
+    w = synth.make("logistic64")
+    ts = w.panel
+    ids = np.arange(64)
+    _say("simplex logistic64 E=1..10")
+    optE, rho = ccm.simplex_optE(_cuda(ts), ids, 1, 10, 1, 1, ccm.MODE_LOO)
+    oE, oR, _ = O.simplex_optE(ts, ids, 1, 10, 1, 1)
+    _check_optE(optE.cpu().numpy(), rho.cpu().numpy(), oE, oR, "logistic64")
+
+
+def test_optE_ratenet_sample_and_half_mode(ccm):
+    w = synth.make("ratenet1024")
+    ts = w.panel
+    ids = np.array([3, 500, 1021], dtype=np.int32)
+    _say("simplex ratenet1024 sample E=1..20")
+    optE, rho = ccm.simplex_optE(_cuda(ts), ids, 1, 20, 1, 1, ccm.MODE_LOO)
+    oE, oR, _ = O.simplex_optE(ts, ids, 1, 20, 1, 1)
+    _check_optE(optE.cpu().numpy(), rho.cpu().numpy(), oE, oR, "ratenet LOO")
+    _say("simplex HALF / tau=2 / E=3..8")
+    optE, rho = ccm.simplex_optE(_cuda(ts), ids, 3, 8, 2, 1, ccm.MODE_HALF)
+    oE, oR, _ = O.simplex_optE(ts, ids, 3, 8, 2, 1, O.MODE_HALF)
+    _check_optE(optE.cpu().numpy(), rho.cpu().numpy(), oE, oR, "ratenet HALF")
+
+
+def test_optE_degenerate_constant(ccm):
+    ts = np.ones((60, 2), dtype=np.float32)
+    ts[:, 1] = np.arange(60) % 2
+    _say("simplex constant series")
+    optE, rho = ccm.simplex_optE(_cuda(ts), [0], 2, 5, 1, 1)
+    assert optE.item() == 2 and np.all(np.isnan(rho.cpu().numpy()))
+
+
+# ---------------------------------------------------------------------------------------
+def _check_rho(rho_g, rho_o, label, tol=RHO_TOL):
+    assert np.array_equal(np.isnan(rho_g), np.isnan(rho_o)), f"{label}: NaN pattern differs"
+    d = np.abs(rho_g.astype(np.float64) - rho_o)[~np.isnan(rho_o)]
+    print(f"{label}: |drho| max {d.max():.3e} p99 {np.quantile(d, 0.99):.3e} "
+          f"median {np.median(d):.3e}")
+    assert d.max() < tol, f"{label}: max |drho| {d.max()}"
+
+
+def test_crossmap_logistic64_full_block(ccm):
+    w = synth.make("logistic64")
+    ts = w.panel
+    oE, _, _ = O.simplex_optE(ts, np.arange(64), 1, 10, 1, 1)
+    _say("crossmap logistic64 64x64")
+    idx, wt, _ = ccm.knn(_cuda(ts), np.arange(64), oE, k_max=11)
+    rho = ccm.crossmap_rho(_cuda(ts), idx, wt, oE).cpu().numpy()
+    rho_o, idx_o, _, _ = O.ccm_block(ts, np.arange(64), oE, 1, 0, 64, k_max=11)
+    assert np.array_equal(idx.cpu().numpy(), idx_o)
+    _check_rho(rho, rho_o, "logistic64")
+
+
+def test_crossmap_ratenet_ragged_targets(ccm):
+    w = synth.make("ratenet1024")
+    ts = w.panel
+    lib_ids = np.arange(5, 1024, 41, dtype=np.int32)  # 25 libraries
+    lib_E = (np.arange(25) * 7 % 20 + 1).astype(np.int32)
+    tgt0, n_tgt = 7, 1001  # ragged last tile
+    _say("crossmap ratenet1024 25 libs x 1001 targets")
+    idx, wt, _ = ccm.knn(_cuda(ts), lib_ids, lib_E, k_max=21)
+    rho, mom = ccm.crossmap_rho(_cuda(ts), idx, wt, lib_E, tgt0=tgt0, n_tgt=n_tgt,
+                                want_moments=True)
+    idx_o, w_o, _ = O.knn(ts, lib_ids, lib_E, 1, 0, 21)
+    assert np.array_equal(idx.cpu().numpy(), idx_o)
+    rho_o = O.crossmap_rho(ts, idx_o, w_o, lib_E, 1, tgt0, n_tgt)
+    _check_rho(rho.cpu().numpy(), rho_o, "ratenet1024")
+    # moments: sum(yhat) against the oracle prediction for one pair
+    i, j = 3, 500
+    E = int(lib_E[i])
+    Q = np.arange(E - 1, ts.shape[0])
+    y = ts[:, tgt0 + j].astype(np.float64)
+    yhat = np.sum(w_o[i][Q, : E + 1] * y[idx_o[i][Q, : E + 1]], axis=1)
+    m = mom.cpu().numpy()[i, j]
+    np.testing.assert_allclose(m, [yhat.sum(), (yhat * yhat).sum(), (y[Q] * yhat).sum()],
+                               rtol=1e-5, atol=1e-3)
+
+
+def test_crossmap_nan_for_constant_target_and_bad_library(ccm):
+    rng = np.random.default_rng(9)
+    ts = rng.standard_normal((120, 20)).astype(np.float32)
+    ts[:, 4] = 2.0
+    lib_E = np.array([3, 2, 0], dtype=np.int32)  # third library unusable
+    _say("crossmap NaN cases")
+    idx, wt, _ = ccm.knn(_cuda(ts), [0, 1, 2], lib_E, k_max=4)
+    rho = ccm.crossmap_rho(_cuda(ts), idx, wt, lib_E).cpu().numpy()
+    assert np.all(np.isnan(rho[:, 4])) and np.all(np.isnan(rho[2]))
+    idx_o, w_o, _ = O.knn(ts, [0, 1], lib_E[:2], 1, 0, 4)
+    rho_o = O.crossmap_rho(ts, idx_o, w_o, lib_E[:2], 1, 0, 20)
+    _check_rho(rho[:2], rho_o, "small")
