@@ -1,0 +1,249 @@
+"""Benchmark of the all-pairs CCM hot path on one MI355X.
+
+One step = the whole hot path over one batch of synthetic input that is already resident
+in HBM: simplex optE for every library (E = 1..20, Tp = 1, leave-one-out) -> neighbour
+tables at each library's optE (Tp = 0) -> FP32 cross-map of every library against every
+target, reduced to Pearson rho.  The workload is the 512-library x 101,729-target block at
+L = 1600 (filtered-Poisson rates of a 101,729-unit sparse rate network, z-scored).
+
+Prints ONE JSON line.  `value` = library x target cross-maps per second of the whole step.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cross-maps/s (library x target rho), FP32 gather vs BF16-MFMA, % HBM/MFMA peak"
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def gather_model_bytes(lib_E, L: int, n_tgt: int) -> float:
+    """Algorithmic bytes of one FP32 cross-map launch: per cross-map 4 n_E (target column
+    read once) + 4 (rho), plus the library's table (8 k L bytes) read once."""
+    lib_E = np.asarray(lib_E, dtype=np.int64)
+    n = L - lib_E + 1
+    k = lib_E + 1
+    return float(np.sum(n_tgt * (4.0 * n + 4.0) + 8.0 * k * L))
+
+
+def mfma_flops(lib_E, L: int, n_tgt: int) -> float:
+    """Dense MFMA work of the BF16 densified form: 2 * n_E * L per cross-map."""
+    lib_E = np.asarray(lib_E, dtype=np.int64)
+    n = L - lib_E + 1
+    return float(np.sum(2.0 * n * L) * n_tgt)
+
+
+def source_hash(*names) -> str:
+    h = hashlib.sha1()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2011_11082_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:12]
+
+
+def load_traffic(kernel_src: str, launches_per_call: int = 1):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was taken on
+    the current kernel source (else None)."""
+    p = os.path.join(ROOT, "profiles", "gather_fp32_brain101729_pmc.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("source_hash") != source_hash(kernel_src):
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(panel, lib_E_gpu, n_lib_total: int, n_tgt_total: int, L: int, budget_s: float):
+    """Time the CPU oracle on a bounded sample and scale to the metric's unit."""
+    import oracle as O
+
+    libs = [0, 1]
+    n_t = 256
+    tgt = np.arange(0, n_tgt_total, max(1, n_tgt_total // n_t))[:n_t]
+    t0 = time.perf_counter()
+    per_lib = []
+    per_pair = []
+    out = {}
+    for li in libs:
+        a = time.perf_counter()
+        oE, _, _ = O.simplex_optE(panel, [li], 1, 20, 1, 1)
+        E = int(oE[0])
+        idx, w, d2 = O.knn(panel, [li], [E], 1, 0, 21)
+        b = time.perf_counter()
+        sub = np.ascontiguousarray(panel[:, tgt])
+        rho = O.crossmap_rho(sub, idx, w, [E], 1, 0, len(tgt))
+        c = time.perf_counter()
+        per_lib.append(b - a)
+        per_pair.append((c - b) / len(tgt))
+        out[li] = (E, idx, rho)
+        if time.perf_counter() - t0 > budget_s:
+            break
+    t_lib = float(np.mean(per_lib))
+    t_pair = float(np.mean(per_pair))
+    total = n_lib_total * t_lib + n_lib_total * n_tgt_total * t_pair
+    return {
+        "value": n_lib_total * n_tgt_total / total,
+        "unit": "cross-maps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{len(per_lib)} libraries: optE E=1..20 + table ({t_lib:.2f} s each), "
+                   f"cross-map vs {n_t} targets ({t_pair * 1e6:.0f} us per pair); scaled to "
+                   f"{n_lib_total} x {n_tgt_total} (extrapolated, single process)"),
+    }, out, tgt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="brain101729")
+    ap.add_argument("--n-lib", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--profile-steps", action="store_true",
+                    help="no timing extras (for runs under rocprofv3)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not "
+                          "part of it (libraries would shard across GPUs with no exchange)"}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2011_11082_amd as ccm
+    import synth
+
+    ccm.load_library()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+
+    t = time.perf_counter()
+    wl = synth.make(args.workload)
+    log(f"workload {args.workload} {wl.panel.shape} ready in {time.perf_counter() - t:.1f} s")
+    panel = wl.panel
+    L, N = panel.shape
+    lib_ids_np = wl.lib_ids if args.n_lib is None else wl.lib_ids[: args.n_lib]
+    n_lib = len(lib_ids_np)
+    n_tgt = wl.n_tgt
+    ts = torch.as_tensor(panel).to(dev)
+    lib_ids = torch.as_tensor(lib_ids_np, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def step(record=None):
+        optE, rho_E = ccm.simplex_optE(ts, lib_ids, 1, wl.E_max, 1, 1, ccm.MODE_LOO)
+        e1 = ev(); e1.record()
+        idx, w, _ = ccm.knn(ts, lib_ids, optE, 1, 0, 21, want_d2=False)
+        e2 = ev(); e2.record()
+        rho = ccm.crossmap_rho(ts, idx, w, optE, 1, wl.tgt0, n_tgt, ccm.PRECISION_FP32)
+        e3 = ev(); e3.record()
+        if record is not None:
+            record.append((e1, e2, e3))
+        return optE, idx, w, rho
+
+    for i in range(args.warmup):
+        step()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+
+    marks = []
+    starts = []
+    t0 = ev(); t0.record()
+    wall0 = time.perf_counter()
+    for i in range(args.steps):
+        s = ev(); s.record(); starts.append(s)
+        out = step(marks)
+    t1 = ev(); t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t0.elapsed_time(t1)
+    ms_step = total_ms / args.steps
+    t_opt = np.mean([s.elapsed_time(m[0]) for s, m in zip(starts, marks)])
+    t_knn = np.mean([m[0].elapsed_time(m[1]) for m in marks])
+    t_cm = np.mean([m[1].elapsed_time(m[2]) for m in marks])
+    log(f"timed {args.steps} steps: {ms_step:.2f} ms/step (optE {t_opt:.2f}, knn {t_knn:.2f}, "
+        f"crossmap {t_cm:.2f}); wall {wall:.2f} s")
+    optE, idx, w, rho = out
+    optE_np = optE.cpu().numpy()
+    cross = float(n_lib) * n_tgt
+    value = cross / (ms_step * 1e-3)
+
+    model_bytes = gather_model_bytes(optE_np, L, n_tgt)
+    achieved = model_bytes / (t_cm * 1e-3) / 1e9
+    traffic = load_traffic("crossmap.hip")
+    roofline = {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "kernel": "ccm_crossmap_rho FP32 (table prep + gather)",
+        "model_bytes_per_launch": model_bytes, "launch_ms": round(float(t_cm), 3),
+    }
+
+    res = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "cross-maps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{args.workload}: {n_lib} libraries x {n_tgt} targets, L={L}, "
+                         "filtered-Poisson rates of a sparse rate network (z-scored); "
+                         "optE E=1..20 (LOO, Tp=1) -> tables at optE (k=E+1) -> FP32 cross-map"),
+            "n_lib": n_lib, "n_tgt": n_tgt, "L": L,
+        },
+        "breakdown_ms": {"simplex_optE": round(float(t_opt), 3), "knn": round(float(t_knn), 3),
+                         "crossmap_fp32": round(float(t_cm), 3)},
+        "crossmap_fp32_rate": round(cross / (t_cm * 1e-3), 1),
+        "optE_hist": np.bincount(optE_np, minlength=21)[1:].tolist(),
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu_baseline and not args.profile_steps:
+        log("timing the CPU oracle on a bounded sample")
+        cb, oracle_out, tgt = cpu_baseline(panel, optE_np, n_lib, n_tgt, L, args.cpu_budget)
+        res["cpu_baseline"] = cb
+        # parity on the same sample
+        idx_np = idx.cpu().numpy()
+        rho_np = rho.cpu().numpy()
+        pe = {}
+        worst = 0.0
+        exact = True
+        for li, (E, oidx, orho) in oracle_out.items():
+            if int(optE_np[li]) != E:
+                pe[f"optE_{li}"] = [int(optE_np[li]), E]
+                continue
+            exact &= bool(np.array_equal(idx_np[li], oidx[0]))
+            worst = max(worst, float(np.nanmax(np.abs(rho_np[li, tgt] - orho[0]))))
+        pe["knn_bit_exact"] = exact
+        pe["max_abs_drho"] = worst
+        res["parity_sample"] = pe
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

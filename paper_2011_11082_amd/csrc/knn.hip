@@ -14,7 +14,7 @@
 // candidates arrive in ascending time order, "strictly smaller d^2" is exactly the
 // (d^2, time index) order, so ties go to the lower index with no extra work.
 //
-// Distances follow one canonical FP32 operation sequence (lag 0 first; one rounding per
+// Selection distances follow one canonical FP32 operation sequence (lag 0 first; one rounding per
 // subtraction, product and sum; no fused multiply-add: this file is compiled with
 // -ffp-contract=off), so the selected indices are bit-identical to any implementation
 // that follows the same sequence.  For the E scan of optE the squared distance of E is
@@ -58,15 +58,25 @@ __device__ __forceinline__ void offer_chunk(float cand, int base, float& ld, int
   }
 }
 
-// Simplex weights of a finished list, lanes 0..k-1: u = exp(-d/d1), d = sqrt(d^2); the
-// d1 = 0 limit gives u = 1 on zero distances and 0 elsewhere.  Lanes >= k get 0.
-__device__ __forceinline__ float list_weight(float d2, int k, float& usum) {
-  int lane = lane_id();
-  bool in = lane < k;
-  float d = in ? sqrtf(d2) : 0.0f;
-  float d1 = readlane(d, 0);
-  float u = 0.0f;
-  if (in) u = d1 > 0.0f ? expf(-d / d1) : (d == 0.0f ? 1.0f : 0.0f);
+// Simplex weights of a finished list (lanes 0..k-1 hold neighbour n_j of query t).  The
+// distance of each selected neighbour is recomputed in FP64 from the series (k x E terms,
+// negligible next to the scan), so the weights do not depend on FP32 rounding or
+// underflow of d^2: u = exp(-d/d1); when d1 = 0, u = 1 on zero distances, 0 elsewhere.
+// Returns u (lanes >= k: 0) and the wave-wide sum of u in `usum`.
+__device__ __forceinline__ double list_weight64(const float* x, int t, int nb, int E, int tau,
+                                                int k, double& usum) {
+  const int lane = lane_id();
+  const bool in = lane < k && nb >= 0;
+  double dd = 0.0;
+  if (in)
+    for (int e = 0; e < E; ++e) {
+      double df = (double)x[t - e * tau] - (double)x[nb - e * tau];
+      dd += df * df;
+    }
+  const double d = sqrt(dd);
+  const double d1 = __hiloint2double(readlane(__double2hiint(d), 0), readlane(__double2loint(d), 0));
+  double u = 0.0;
+  if (in) u = d1 > 0.0 ? exp(-d / d1) : (d == 0.0 ? 1.0 : 0.0);
   usum = wave_sum(u);
   return u;
 }
@@ -131,12 +141,12 @@ __global__ __launch_bounds__(256) void knn_table_kernel(const float* __restrict_
       float cand = (inr && s != t) ? acc : INFINITY;
       offer_chunk(cand, base, ldist, lidx, thr, k - 1);
     }
-    float usum;
-    float u = list_weight(ldist, k, usum);
+    double usum;
+    double u = list_weight64(x, t, lidx, E, tau, k, usum);
     if (lane < k_max) {
       bool in = lane < k;
       oi[lane] = in ? lidx : -1;
-      ow[lane] = in ? u / usum : 0.0f;
+      ow[lane] = in ? (float)(u / usum) : 0.0f;
       if (od) od[lane] = in ? ldist : INFINITY;
     }
   }
@@ -210,10 +220,10 @@ __global__ __launch_bounds__(kSimplexThreads) void simplex_kernel(
     for (int e = 0; e < kEMax; ++e) {
       const int E = e + 1;
       if (e < E_max && E >= E_min && t >= qbase + (E - 1) * tau) {
-        float usum;
-        float u = list_weight(ldist[e], E + 1, usum);
-        float f = lane <= E ? x[lidx[e] + Tp] : 0.0f;
-        float pred = wave_sum(u * f) / usum;
+        double usum;
+        double u = list_weight64(x, t, lidx[e], E, tau, E + 1, usum);
+        double f = (lane <= E && lidx[e] >= 0) ? (double)x[lidx[e] + Tp] : 0.0;
+        double pred = wave_sum(u * f) / usum;
         if (lane == e) {
           double o = obs, p = pred;
           m_o += o;

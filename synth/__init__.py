@@ -109,6 +109,21 @@ def _sparse_gaussian(rng: np.random.Generator, N: int, p: float):
     return J
 
 
+def _row_split_matvec(J, min_rows: int = 16384):
+    """J @ v computed over row blocks in threads (each row's dot product is the same
+    arithmetic as the unsplit product, so the result is bitwise identical)."""
+    N = J.shape[0]
+    nt = min(16, os.cpu_count() or 1)
+    if N < min_rows or nt < 2:
+        return lambda v: J @ v
+    from concurrent.futures import ThreadPoolExecutor
+
+    bounds = np.linspace(0, N, nt + 1).astype(int)
+    parts = [J[bounds[i]: bounds[i + 1]] for i in range(nt)]
+    pool = ThreadPoolExecutor(nt)
+    return lambda v: np.concatenate(list(pool.map(lambda P: P @ v, parts)))
+
+
 def rate_network(rng: np.random.Generator, N: int, T: int, *, p=0.01, g=1.5, dt=0.1,
                  sigma=0.05, burn=1000, poisson=False, lam_max=1.0, tau_f=5.0):
     """Sparse random recurrent rate network of tanh units.
@@ -123,13 +138,14 @@ def rate_network(rng: np.random.Generator, N: int, T: int, *, p=0.01, g=1.5, dt=
     Returns the raw (not z-scored) float64 panel [T][N].
     """
     J = _sparse_gaussian(rng, N, p)
+    matvec = _row_split_matvec(J)
     x = rng.standard_normal(N)
     decay = np.exp(-1.0 / tau_f)
     f = np.zeros(N)
     out = np.empty((T, N), dtype=np.float64)
     for step in range(burn + T):
         r = np.tanh(x)
-        x = x + dt * (-x + g * (J @ r)) + sigma * rng.standard_normal(N)
+        x = x + dt * (-x + g * matvec(r)) + sigma * rng.standard_normal(N)
         r = np.tanh(x)
         if poisson:
             s = rng.poisson(lam_max * 0.5 * (1.0 + r))
