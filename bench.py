@@ -116,9 +116,13 @@ def main():
     ap.add_argument("--workload", default="brain101729")
     ap.add_argument("--n-lib", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--profile-steps", action="store_true",
                     help="no timing extras (for runs under rocprofv3)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (a known-size "
+                         "reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -134,6 +138,16 @@ def main():
     ccm.load_library()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+
+    if args.copy_calibration_mib:
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.copy_calibration_mib} MiB done")
+        del src, dst
 
     t = time.perf_counter()
     wl = synth.make(args.workload)
@@ -223,6 +237,34 @@ def main():
         "roofline": roofline,
     }
 
+    # BF16-MFMA form on the same tables (not part of the step; reported beside it)
+    rho_bf = None
+    if not args.no_bf16:
+        for _ in range(1):
+            ccm.crossmap_rho(ts, idx, w, optE, 1, wl.tgt0, n_tgt, ccm.PRECISION_BF16)
+        torch.cuda.synchronize()
+        eb0 = ev(); eb0.record()
+        nb = max(1, min(3, args.steps))
+        for _ in range(nb):
+            rho_bf = ccm.crossmap_rho(ts, idx, w, optE, 1, wl.tgt0, n_tgt, ccm.PRECISION_BF16)
+        eb1 = ev(); eb1.record()
+        torch.cuda.synchronize()
+        t_bf = eb0.elapsed_time(eb1) / nb
+        flops = mfma_flops(optE_np, L, n_tgt)
+        d = (rho_bf - rho).abs()
+        d = d[~torch.isnan(d)]
+        res["bf16"] = {
+            "crossmap_ms": round(float(t_bf), 3),
+            "rate": round(cross / (t_bf * 1e-3), 1),
+            "speedup_vs_fp32": round(float(t_cm / t_bf), 4),
+            "mfma": {"bound": "mfma", "achieved": round(flops / (t_bf * 1e-3) / 1e12, 1),
+                     "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(flops / (t_bf * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4),
+                     "dense_flops_per_launch": flops},
+            "max_abs_drho_vs_fp32": float(d.max()) if d.numel() else None,
+        }
+        log(f"bf16 crossmap {t_bf:.2f} ms")
+
     if not args.no_cpu_baseline and not args.profile_steps:
         log("timing the CPU oracle on a bounded sample")
         cb, oracle_out, tgt = cpu_baseline(panel, optE_np, n_lib, n_tgt, L, args.cpu_budget)
@@ -239,6 +281,9 @@ def main():
                 continue
             exact &= bool(np.array_equal(idx_np[li], oidx[0]))
             worst = max(worst, float(np.nanmax(np.abs(rho_np[li, tgt] - orho[0]))))
+            if rho_bf is not None:
+                wb = float(np.nanmax(np.abs(rho_bf[li, tgt].cpu().numpy() - orho[0])))
+                pe["bf16_max_abs_drho"] = max(pe.get("bf16_max_abs_drho", 0.0), wb)
         pe["knn_bit_exact"] = exact
         pe["max_abs_drho"] = worst
         res["parity_sample"] = pe

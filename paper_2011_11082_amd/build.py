@@ -24,6 +24,7 @@ COMMON = [
 SOURCES = {
     "knn.hip": ["-ffp-contract=off"],
     "crossmap.hip": [],
+    "crossmap_bf16.hip": [],
     "ccm_abi.cpp": ["-x", "hip"],
 }
 

@@ -16,7 +16,7 @@ hipError_t ccm_launch_knn(const float* ts, int64_t ld, int L, const int* lib_ids
                           float* nbr_d2, hipStream_t stream);
 hipError_t ccm_launch_simplex(const float* ts, int64_t ld, int L, const int* ids, int n, int E_min,
                               int E_max, int tau, int Tp, int mode, int* optE, float* rho_E,
-                              hipStream_t stream);
+                              double* rho64, hipStream_t stream);
 hipError_t ccm_launch_embed(const float* ts, int64_t ld, int L, const int* ids, int n, int E,
                             int tau, float* emb, hipStream_t stream);
 size_t ccm_gather_lds_bytes(int L);
@@ -25,6 +25,12 @@ hipError_t ccm_launch_crossmap_fp32(const float* ts, int64_t ld, int L, int tau,
                                     const int* lib_E, int n_lib, int k_max, float* rho,
                                     double* moments, uint32_t* poff, float* pw, int* lib_k,
                                     int* order, hipStream_t stream);
+size_t ccm_bf16_lds_bytes();
+hipError_t ccm_launch_crossmap_bf16(const float* ts, int64_t ld, int L, int tau, int tgt0, int n_tgt,
+                                    const int* nbr_idx, const float* nbr_w, const int* lib_E,
+                                    int n_lib, int k_max, float* rho, double* moments, uint16_t* yt,
+                                    uint32_t* ent, int* stage_off, int* lib_k, int* order,
+                                    hipStream_t stream);
 }
 
 namespace {
@@ -57,6 +63,25 @@ CrossmapWs crossmap_ws(int L, int n_lib, int k_max) {
   w.off_poff = 0;
   w.off_pw = align_up(w.off_poff + ent * 4);
   w.off_libk = align_up(w.off_pw + ent * 4);
+  w.off_order = align_up(w.off_libk + (size_t)n_lib * 4);
+  w.total = align_up(w.off_order + (size_t)n_lib * 4);
+  return w;
+}
+
+// Workspace of the BF16 cross-map: BF16 target panel (target-major), stage-sorted table
+// entries, stage offsets, lib_k, order.
+struct Bf16Ws {
+  size_t off_yt, off_ent, off_so, off_libk, off_order, total;
+};
+
+Bf16Ws bf16_ws(int L, int n_lib, int n_tgt) {
+  Bf16Ws w;
+  const size_t nst = (size_t)(L + 63) / 64;
+  const size_t nch = (size_t)(L + 127) / 128;
+  w.off_yt = 0;
+  w.off_ent = align_up(w.off_yt + (size_t)n_tgt * nst * 64 * 2);
+  w.off_so = align_up(w.off_ent + (size_t)n_lib * nch * 128 * CCM_K_MAX * 4);
+  w.off_libk = align_up(w.off_so + (size_t)n_lib * nch * (nst + 1) * 4);
   w.off_order = align_up(w.off_libk + (size_t)n_lib * 4);
   w.total = align_up(w.off_order + (size_t)n_lib * 4);
   return w;
@@ -99,13 +124,17 @@ ccm_status ccm_workspace_size(int32_t op, int32_t L, int32_t n_lib, int32_t n_tg
   switch (op) {
     case CCM_OP_EMBED:
     case CCM_OP_KNN:
-    case CCM_OP_SIMPLEX:
       *bytes = 0;
+      return CCM_OK;
+    case CCM_OP_SIMPLEX:  // FP64 skill per (series, E); n_lib = number of series
+      *bytes = align_up((size_t)n_lib * CCM_E_MAX * sizeof(double));
       return CCM_OK;
     case CCM_OP_CROSSMAP_FP32:
       *bytes = crossmap_ws(L, n_lib, k_max).total;
       return CCM_OK;
     case CCM_OP_CROSSMAP_BF16:
+      *bytes = bf16_ws(L, n_lib, n_tgt).total;
+      return CCM_OK;
     case CCM_OP_CROSSMAP_BACKWARD:
       *bytes = 0;
       return CCM_OK;
@@ -147,8 +176,6 @@ ccm_status ccm_knn(const float* ts, int64_t ld, int32_t L, const int32_t* lib_id
 ccm_status ccm_simplex_optE(const float* ts, int64_t ld, int32_t L, const int32_t* ids, int32_t n,
                             int32_t E_min, int32_t E_max, int32_t tau, int32_t Tp, int32_t mode,
                             int32_t* optE, float* rho_E, void* ws, size_t ws_bytes, void* stream) {
-  (void)ws;
-  (void)ws_bytes;
   const char* fn = "ccm_simplex_optE";
   ccm_status st = CCM_OK;
   if (!check_series(fn, &st, ts, ld, L, tau)) return st;
@@ -166,8 +193,11 @@ ccm_status ccm_simplex_optE(const float* ts, int64_t ld, int32_t L, const int32_
   else
     ncand = (L / 2 - 1 - Tp) - lo + 1;
   if (ncand < E_max + 1) return fail(CCM_ERANGE, fn, "too few points for k = E_max + 1 neighbours");
+  if (n == 0) return CCM_OK;
+  const size_t need = align_up((size_t)n * CCM_E_MAX * sizeof(double));
+  if (!ws || ws_bytes < need) return fail(CCM_EWORKSPACE, fn, "workspace too small");
   return device_status(fn, ccm_launch_simplex(ts, ld, L, ids, n, E_min, E_max, tau, Tp, mode, optE,
-                                              rho_E, (hipStream_t)stream));
+                                              rho_E, (double*)ws, (hipStream_t)stream));
 }
 
 ccm_status ccm_crossmap_rho(const float* ts, int64_t ld, int32_t L, const int32_t* nbr_idx,
@@ -196,7 +226,18 @@ ccm_status ccm_crossmap_rho(const float* ts, int64_t ld, int32_t L, const int32_
                                      (float*)(base + w.off_pw), (int*)(base + w.off_libk),
                                      (int*)(base + w.off_order), (hipStream_t)stream));
   }
-  if (precision == CCM_PRECISION_BF16) return fail(CCM_ENOTSUP, fn, "BF16 form not built yet");
+  if (precision == CCM_PRECISION_BF16) {
+    Bf16Ws w = bf16_ws(L, n_lib, n_tgt);
+    if (n_lib == 0 || n_tgt == 0) return CCM_OK;
+    if (!ws || ws_bytes < w.total) return fail(CCM_EWORKSPACE, fn, "workspace too small");
+    char* base = (char*)ws;
+    return device_status(
+        fn, ccm_launch_crossmap_bf16(ts, ld, L, tau, tgt0, n_tgt, nbr_idx, nbr_w, lib_E, n_lib, k_max,
+                                     rho, moments, (uint16_t*)(base + w.off_yt),
+                                     (uint32_t*)(base + w.off_ent), (int*)(base + w.off_so),
+                                     (int*)(base + w.off_libk), (int*)(base + w.off_order),
+                                     (hipStream_t)stream));
+  }
   return fail(CCM_EINVAL, fn, "unknown precision");
 }
 

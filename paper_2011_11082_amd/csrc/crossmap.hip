@@ -137,16 +137,113 @@ __global__ __launch_bounds__(256) void prep_tables_kernel(
 // The gather.  grid = (target tiles, library splits), block = 1024 threads.
 // LDS: tile [L][16] floats, then column sums sy[E][16], syy[E][16] (FP64, E = 1..20).
 // ---------------------------------------------------------------------------------------
-template <int J>
-__device__ __forceinline__ void gather_step(const char* tile, const uint32_t (&off)[6],
-                                            const float (&wgt)[6], uint32_t laneoff, float4& acc) {
-  const uint32_t o = (uint32_t)quad_bcast<J & 3>((int)off[J >> 2]) + laneoff;
-  const float4 y = *(const float4*)(tile + o);
-  const float w = quad_bcast<J & 3>(wgt[J >> 2]);
-  acc.x = fmaf(w, y.x, acc.x);
-  acc.y = fmaf(w, y.y, acc.y);
-  acc.z = fmaf(w, y.z, acc.z);
-  acc.w = fmaf(w, y.w, acc.w);
+// Steps J .. J+3 of one table row: the four 128-bit LDS reads are issued before any of
+// their products, so several reads are in flight per wave.
+template <int J, int K>
+__device__ __forceinline__ void gather_quad(const char* tile, const uint32_t (&off)[(K + 3) / 4],
+                                            const float (&wgt)[(K + 3) / 4], uint32_t laneoff,
+                                            float4& acc) {
+  constexpr int S = J >> 2;
+  float4 y[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (J + q < K) {
+      uint32_t o;
+      if (q == 0) o = (uint32_t)quad_bcast<0>((int)off[S]);
+      if (q == 1) o = (uint32_t)quad_bcast<1>((int)off[S]);
+      if (q == 2) o = (uint32_t)quad_bcast<2>((int)off[S]);
+      if (q == 3) o = (uint32_t)quad_bcast<3>((int)off[S]);
+      y[q] = *(const float4*)(tile + o + laneoff);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (J + q < K) {
+      float w;
+      if (q == 0) w = quad_bcast<0>(wgt[S]);
+      if (q == 1) w = quad_bcast<1>(wgt[S]);
+      if (q == 2) w = quad_bcast<2>(wgt[S]);
+      if (q == 3) w = quad_bcast<3>(wgt[S]);
+      acc.x = fmaf(w, y[q].x, acc.x);
+      acc.y = fmaf(w, y[q].y, acc.y);
+      acc.z = fmaf(w, y[q].z, acc.z);
+      acc.w = fmaf(w, y[q].w, acc.w);
+    }
+  }
+}
+
+template <int K, int J = 0>
+__device__ __forceinline__ void gather_row(const char* tile, const uint32_t (&off)[(K + 3) / 4],
+                                           const float (&wgt)[(K + 3) / 4], uint32_t laneoff,
+                                           float4& acc) {
+  if constexpr (J < K) {
+    gather_quad<J, K>(tile, off, wgt, laneoff, acc);
+    gather_row<K, J + 4>(tile, off, wgt, laneoff, acc);
+  }
+}
+
+struct Moments {
+  float4 sp, spp, syp;
+  double dp[4], dpp[4], dyp[4];
+};
+
+__device__ __forceinline__ void fold(Moments& m) {
+  m.dp[0] += m.sp.x; m.dp[1] += m.sp.y; m.dp[2] += m.sp.z; m.dp[3] += m.sp.w;
+  m.dpp[0] += m.spp.x; m.dpp[1] += m.spp.y; m.dpp[2] += m.spp.z; m.dpp[3] += m.spp.w;
+  m.dyp[0] += m.syp.x; m.dyp[1] += m.syp.y; m.dyp[2] += m.syp.z; m.dyp[3] += m.syp.w;
+  m.sp = m.spp = m.syp = float4{0, 0, 0, 0};
+}
+
+// One library against the tile: 16 query times per block step, all K products unrolled,
+// next block's table entries loaded while this one is summed.  Rows outside the query
+// range carry weight 0 (prediction exactly 0), so they add nothing to the moments.
+template <int K>
+__device__ __forceinline__ void gather_library(const char* smem, const uint32_t* __restrict__ po,
+                                               const float* __restrict__ pq, int b0, int nblk,
+                                               int KSM, int L, int G, uint32_t laneoff,
+                                               Moments& m) {
+  constexpr int KS = (K + 3) / 4;
+  const int lane = lane_id();
+  uint32_t off[KS];
+  float wgt[KS];
+#pragma unroll
+  for (int s4 = 0; s4 < KS; ++s4) {
+    const size_t p = ((size_t)b0 * KSM + s4) * kWave + lane;
+    off[s4] = po[p];
+    wgt[s4] = pq[p];
+  }
+  int since = 0;
+  for (int b = b0; b < nblk; ++b) {
+    uint32_t offn[KS];
+    float wgtn[KS];
+    const int bn = b + 1 < nblk ? b + 1 : b;
+#pragma unroll
+    for (int s4 = 0; s4 < KS; ++s4) {
+      const size_t p = ((size_t)bn * KSM + s4) * kWave + lane;
+      offn[s4] = po[p];
+      wgtn[s4] = pq[p];
+    }
+    float4 acc = {0, 0, 0, 0};
+    gather_row<K>(smem, off, wgt, laneoff, acc);
+    int t = b * 16 + G;
+    t = t < L ? t : L - 1;
+    const float4 yo = *(const float4*)(smem + (size_t)t * kRowBytes + laneoff);
+    m.sp.x += acc.x; m.sp.y += acc.y; m.sp.z += acc.z; m.sp.w += acc.w;
+    m.spp.x = fmaf(acc.x, acc.x, m.spp.x); m.spp.y = fmaf(acc.y, acc.y, m.spp.y);
+    m.spp.z = fmaf(acc.z, acc.z, m.spp.z); m.spp.w = fmaf(acc.w, acc.w, m.spp.w);
+    m.syp.x = fmaf(yo.x, acc.x, m.syp.x); m.syp.y = fmaf(yo.y, acc.y, m.syp.y);
+    m.syp.z = fmaf(yo.z, acc.z, m.syp.z); m.syp.w = fmaf(yo.w, acc.w, m.syp.w);
+    if (++since == 8) {
+      since = 0;
+      fold(m);
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < KS; ++s4) {
+      off[s4] = offn[s4];
+      wgt[s4] = wgtn[s4];
+    }
+  }
+  fold(m);
 }
 
 __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
@@ -184,7 +281,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
   __syncthreads();
 
   const int lane = lane_id();
-  const int wave = threadIdx.x / kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int nw = blockDim.x / kWave;
   const int G = lane >> 2;
   const int l = lane & 3;
@@ -193,8 +290,8 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
   const size_t libstride = (size_t)nblk * KSM * kWave;
 
   for (int li = blockIdx.y + splits * wave; li < n_lib; li += splits * nw) {
-    const int i = order[li];
-    const int k = lib_k[i];
+    const int i = __builtin_amdgcn_readfirstlane(order[li]);
+    const int k = __builtin_amdgcn_readfirstlane(lib_k[i]);
     if (k == 0) {
       if (lane < kTJ && j0 + lane < n_tgt) {
         rho[(size_t)i * n_tgt + j0 + lane] = __builtin_nanf("");
@@ -207,76 +304,30 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
     }
     const int E = k - 1;
     const int lo = (E - 1) * tau;
-    const int KS = (k + 3) >> 2;
     const uint32_t* po = poff + (size_t)i * libstride;
     const float* pq = pw + (size_t)i * libstride;
-    float4 sp = {0, 0, 0, 0}, spp = {0, 0, 0, 0}, syp = {0, 0, 0, 0};
-    double dp[4] = {0, 0, 0, 0}, dpp[4] = {0, 0, 0, 0}, dyp[4] = {0, 0, 0, 0};
-    int since = 0;
-    for (int b = lo >> 4; b < nblk; ++b) {
-      uint32_t off[6];
-      float wgt[6];
+    Moments m;
+    m.sp = m.spp = m.syp = float4{0, 0, 0, 0};
 #pragma unroll
-      for (int s4 = 0; s4 < 6; ++s4) {
-        if (s4 < KS) {
-          const size_t p = ((size_t)b * KSM + s4) * kWave + lane;
-          off[s4] = po[p];
-          wgt[s4] = pq[p];
-        } else {
-          off[s4] = 0;
-          wgt[s4] = 0.0f;
-        }
-      }
-      float4 acc = {0, 0, 0, 0};
-      gather_step<0>(smem, off, wgt, laneoff, acc);
-      gather_step<1>(smem, off, wgt, laneoff, acc);
-      if (k > 2) gather_step<2>(smem, off, wgt, laneoff, acc);
-      if (k > 3) gather_step<3>(smem, off, wgt, laneoff, acc);
-      if (k > 4) gather_step<4>(smem, off, wgt, laneoff, acc);
-      if (k > 5) gather_step<5>(smem, off, wgt, laneoff, acc);
-      if (k > 6) gather_step<6>(smem, off, wgt, laneoff, acc);
-      if (k > 7) gather_step<7>(smem, off, wgt, laneoff, acc);
-      if (k > 8) gather_step<8>(smem, off, wgt, laneoff, acc);
-      if (k > 9) gather_step<9>(smem, off, wgt, laneoff, acc);
-      if (k > 10) gather_step<10>(smem, off, wgt, laneoff, acc);
-      if (k > 11) gather_step<11>(smem, off, wgt, laneoff, acc);
-      if (k > 12) gather_step<12>(smem, off, wgt, laneoff, acc);
-      if (k > 13) gather_step<13>(smem, off, wgt, laneoff, acc);
-      if (k > 14) gather_step<14>(smem, off, wgt, laneoff, acc);
-      if (k > 15) gather_step<15>(smem, off, wgt, laneoff, acc);
-      if (k > 16) gather_step<16>(smem, off, wgt, laneoff, acc);
-      if (k > 17) gather_step<17>(smem, off, wgt, laneoff, acc);
-      if (k > 18) gather_step<18>(smem, off, wgt, laneoff, acc);
-      if (k > 19) gather_step<19>(smem, off, wgt, laneoff, acc);
-      if (k > 20) gather_step<20>(smem, off, wgt, laneoff, acc);
-      const int t = b * 16 + G;
-      if (t >= lo && t < L) {
-        const float4 yo = *(const float4*)(smem + (size_t)t * kRowBytes + laneoff);
-        sp.x += acc.x; sp.y += acc.y; sp.z += acc.z; sp.w += acc.w;
-        spp.x = fmaf(acc.x, acc.x, spp.x); spp.y = fmaf(acc.y, acc.y, spp.y);
-        spp.z = fmaf(acc.z, acc.z, spp.z); spp.w = fmaf(acc.w, acc.w, spp.w);
-        syp.x = fmaf(yo.x, acc.x, syp.x); syp.y = fmaf(yo.y, acc.y, syp.y);
-        syp.z = fmaf(yo.z, acc.z, syp.z); syp.w = fmaf(yo.w, acc.w, syp.w);
-      }
-      if (++since == 8) {
-        since = 0;
-        dp[0] += sp.x; dp[1] += sp.y; dp[2] += sp.z; dp[3] += sp.w;
-        dpp[0] += spp.x; dpp[1] += spp.y; dpp[2] += spp.z; dpp[3] += spp.w;
-        dyp[0] += syp.x; dyp[1] += syp.y; dyp[2] += syp.z; dyp[3] += syp.w;
-        sp = spp = syp = float4{0, 0, 0, 0};
-      }
+    for (int c = 0; c < 4; ++c) m.dp[c] = m.dpp[c] = m.dyp[c] = 0.0;
+    const int b0 = lo >> 4;
+    switch (k) {
+#define CCM_K(KK) \
+  case KK: gather_library<KK>(smem, po, pq, b0, nblk, KSM, L, G, laneoff, m); break;
+      CCM_K(2) CCM_K(3) CCM_K(4) CCM_K(5) CCM_K(6) CCM_K(7) CCM_K(8) CCM_K(9) CCM_K(10)
+      CCM_K(11) CCM_K(12) CCM_K(13) CCM_K(14) CCM_K(15) CCM_K(16) CCM_K(17) CCM_K(18)
+      CCM_K(19) CCM_K(20) CCM_K(21)
+#undef CCM_K
+      default: break;
     }
-    dp[0] += sp.x; dp[1] += sp.y; dp[2] += sp.z; dp[3] += sp.w;
-    dpp[0] += spp.x; dpp[1] += spp.y; dpp[2] += spp.z; dpp[3] += spp.w;
-    dyp[0] += syp.x; dyp[1] += syp.y; dyp[2] += syp.z; dyp[3] += syp.w;
     // reduce over the 16 groups (lanes with equal l)
 #pragma unroll
     for (int o = 4; o < kWave; o <<= 1) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        dp[c] += __shfl_xor(dp[c], o);
-        dpp[c] += __shfl_xor(dpp[c], o);
-        dyp[c] += __shfl_xor(dyp[c], o);
+        m.dp[c] += __shfl_xor(m.dp[c], o);
+        m.dpp[c] += __shfl_xor(m.dpp[c], o);
+        m.dyp[c] += __shfl_xor(m.dyp[c], o);
       }
     }
     if (G == 0) {
@@ -286,14 +337,14 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
         const int col = 4 * l + c;
         const int j = j0 + col;
         if (j < n_tgt) {
-          const double r = pearson_from_moments(n, sy[E * kTJ + col], syy[E * kTJ + col], dp[c],
-                                                dpp[c], dyp[c]);
+          const double r = pearson_from_moments(n, sy[E * kTJ + col], syy[E * kTJ + col],
+                                                m.dp[c], m.dpp[c], m.dyp[c]);
           rho[(size_t)i * n_tgt + j] = (float)r;
           if (moments) {
             double* mo = moments + ((size_t)i * n_tgt + j) * 3;
-            mo[0] = dp[c];
-            mo[1] = dpp[c];
-            mo[2] = dyp[c];
+            mo[0] = m.dp[c];
+            mo[1] = m.dpp[c];
+            mo[2] = m.dyp[c];
           }
         }
       }
@@ -302,6 +353,11 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
 }
 
 }  // namespace ccm
+
+extern "C" hipError_t ccm_launch_order(const int* lib_k, int n_lib, int* order, hipStream_t stream) {
+  hipLaunchKernelGGL(ccm::order_kernel, dim3(1), dim3(256), 0, stream, lib_k, n_lib, order);
+  return hipGetLastError();
+}
 
 extern "C" size_t ccm_gather_lds_bytes(int L) {
   return (size_t)L * ccm::kRowBytes + 2 * (ccm::kEMax + 1) * ccm::kTJ * sizeof(double);

@@ -1,0 +1,323 @@
+// Cross-map lookup as a dense BF16 MFMA contraction (not in the paper).
+//
+// The lookup of Alg. 5 (Sec. III-B) is, for one library, yhat = W * Y where W is the
+// n x L matrix holding the simplex weights of row t at the columns of its k neighbours
+// (every other entry 0) and Y is the L x n_tgt target panel.  This form densifies W in
+// tiles and runs the product on the matrix cores: BF16 operands (weights and targets
+// rounded to nearest-even), FP32 accumulation, then the same Pearson epilogue as the FP32
+// gather with the observed targets in FP32 and the moments in FP64.  Distances and
+// weights are computed in FP32/FP64 exactly as for the gather; only the product operands
+// are BF16.  The dense product does L / k times the multiply-adds of the gather, so this
+// form is bound by MFMA throughput.
+//
+// gfx950 design:
+//   * workgroup = 4 waves = 2 libraries (sorted by E) x one tile of 128 targets; each wave
+//     owns 64 rows of a 128-row chunk of its library against the 128 targets: a 64 x 128
+//     FP32 accumulator (2 x 4 tiles of v_mfma_f32_32x32x16_bf16).
+//   * K (the neighbour time s) advances in stages of 64: the workgroup stages Y^T[128][64]
+//     BF16 in LDS (double-buffered, loaded one stage ahead through registers) and each wave
+//     scatters the nonzeros of its 64 rows into its own zeroed A tile [64][64]; after its
+//     products it writes the same positions back to zero (the tile is private to the
+//     wave, so program order is the only ordering needed).  A stage whose A tile
+//     is empty for a wave skips that wave's products.
+//   * Table entries are pre-sorted per (library, 128-row chunk) by stage and packed into
+//     32 bits (row, column within stage, BF16 weight).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "wave.h"
+
+namespace ccm {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+constexpr int kBTN = 128;     // targets per tile
+constexpr int kBRows = 128;   // rows of A per chunk
+constexpr int kHalf = 64;     // rows of A per wave
+constexpr int kStage = 64;    // K per stage
+constexpr int kBThreads = 256;
+constexpr int kMaxStages = 16384 / kStage;  // L <= 16384
+
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+  __bf16 b = (__bf16)f;  // round to nearest even
+  return __builtin_bit_cast(uint16_t, b);
+}
+
+// Y (time-major, FP32) -> Yt [n_tgt][Lpad] BF16, zero beyond L.
+__global__ __launch_bounds__(256) void transpose_bf16_kernel(const float* __restrict__ ts, int64_t ld,
+                                                             int L, int tgt0, int n_tgt, int Lpad,
+                                                             uint16_t* __restrict__ yt) {
+  __shared__ float tile[64][65];
+  const int j0 = blockIdx.x * 64;
+  const int t0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63;
+  const int ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int t = t0 + r, j = j0 + tx;
+    tile[r][tx] = (t < L && j < n_tgt) ? ts[(int64_t)t * ld + tgt0 + j] : 0.0f;
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int j = j0 + r, t = t0 + tx;
+    if (j < n_tgt && t < Lpad) yt[(size_t)j * Lpad + t] = bf16_bits(tile[tx][r]);
+  }
+}
+
+// Per (chunk, library): sort the chunk's table entries by stage.  Entry = row (7 bits) |
+// column within stage (6 bits) << 7 | BF16 weight << 16.  Offsets [nst + 1] per chunk.
+__global__ __launch_bounds__(kBRows) void bf16_entries_kernel(
+    const int* __restrict__ nbr_idx, const float* __restrict__ nbr_w, const int* __restrict__ lib_E,
+    int L, int k_max, int tau, int nchunk_max, int nst, uint32_t* __restrict__ ent,
+    int* __restrict__ stage_off, int* __restrict__ lib_k) {
+  __shared__ int cnt[kMaxStages];
+  __shared__ int cur[kMaxStages];
+  const int c = blockIdx.x;
+  const int i = blockIdx.y;
+  const int E = lib_E[i];
+  const int k = E + 1;
+  const int lo = (E - 1) * tau;
+  bool libok = E >= 1 && E <= kEMax && k <= k_max && (L - lo) >= k + 1;
+  if (libok) libok = nbr_idx[((size_t)i * L + lo) * k_max] >= 0;
+  if (c == 0 && threadIdx.x == 0) lib_k[i] = libok ? k : 0;
+  for (int q = threadIdx.x; q < nst; q += blockDim.x) cnt[q] = 0;
+  __syncthreads();
+  const int row = threadIdx.x;
+  const int t = lo + c * kBRows + row;
+  const bool rowok = libok && t < L;
+  int sidx[kKMax];
+  float wv[kKMax];
+  if (rowok) {
+    for (int m = 0; m < k; ++m) {
+      const int v = nbr_idx[((size_t)i * L + t) * k_max + m];
+      sidx[m] = (v >= 0 && v < L) ? v : -1;
+      wv[m] = nbr_w[((size_t)i * L + t) * k_max + m];
+      if (sidx[m] >= 0) atomicAdd(&cnt[sidx[m] / kStage], 1);
+    }
+  }
+  __syncthreads();
+  int* so = stage_off + ((size_t)i * nchunk_max + c) * (nst + 1);
+  if (threadIdx.x == 0) {
+    int p = 0;
+    for (int q = 0; q < nst; ++q) {
+      cur[q] = p;
+      so[q] = p;
+      p += cnt[q];
+    }
+    so[nst] = p;
+  }
+  __syncthreads();
+  uint32_t* eo = ent + ((size_t)i * nchunk_max + c) * (kBRows * kKMax);
+  if (rowok)
+    for (int m = 0; m < k; ++m)
+      if (sidx[m] >= 0) {
+        const int q = sidx[m] / kStage;
+        const int p = atomicAdd(&cur[q], 1);
+        eo[p] = (uint32_t)row | ((uint32_t)(sidx[m] % kStage) << 7) |
+                ((uint32_t)bf16_bits(wv[m]) << 16);
+      }
+}
+
+__global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
+    const float* __restrict__ ts, int64_t ld, int L, int tau, int tgt0, int n_tgt, int Lpad,
+    const uint16_t* __restrict__ yt, const uint32_t* __restrict__ ent,
+    const int* __restrict__ stage_off, const int* __restrict__ order, const int* __restrict__ lib_k,
+    int n_lib, int nchunk_max, int nst, float* __restrict__ rho, double* __restrict__ moments) {
+  extern __shared__ __align__(16) char smem[];
+  // B: two stages of Yt [128 targets][64 s] BF16 (16 KB each); A: per wave [64 rows][64 s];
+  // moments: per wave [5][4][64] FP64.
+  uint16_t* Bs = (uint16_t*)smem;
+  uint16_t* As = (uint16_t*)(smem + 2 * kBTN * kStage * 2);
+  double* momb = (double*)(smem + 2 * kBTN * kStage * 2 + 4 * kHalf * kStage * 2);
+  const int lane = lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int half = wave & 1;     // rows 64*half .. 64*half+63 of each 128-row chunk
+  const int j0 = blockIdx.x * kBTN;
+  const int li = blockIdx.y * 2 + (wave >> 1);
+  const bool has = li < n_lib;
+  const int i = has ? __builtin_amdgcn_readfirstlane(order[li]) : 0;
+  const int k = has ? __builtin_amdgcn_readfirstlane(lib_k[i]) : 0;
+  const int E = k - 1;
+  const int lo = k > 0 ? (E - 1) * tau : 0;
+  const int nrows = k > 0 ? L - lo : 0;
+  const int nchunk = (nrows + kBRows - 1) / kBRows;
+  __shared__ int s_nchunk[4];
+  if (lane == 0) s_nchunk[wave] = nchunk;
+  uint16_t* Aw = As + (size_t)wave * kHalf * kStage;
+  for (int q = lane; q < kHalf * kStage / 2; q += kWave) ((uint32_t*)Aw)[q] = 0u;
+  double* mom = momb + (size_t)wave * 5 * 4 * kWave;
+#pragma unroll
+  for (int q = 0; q < 20; ++q) mom[q * kWave + lane] = 0.0;
+  __syncthreads();
+  const int nch_all = max(max(s_nchunk[0], s_nchunk[1]), max(s_nchunk[2], s_nchunk[3]));
+
+  // B stage loader: thread -> (target row r = tid/2, half h = tid%2): 64 bytes
+  const int br = threadIdx.x >> 1;
+  const int bh = threadIdx.x & 1;
+  const uint16_t* ysrc = yt + (size_t)(j0 + br) * Lpad + bh * 32;
+  const bool brow_ok = j0 + br < n_tgt;
+
+  for (int c = 0; c < nch_all; ++c) {
+    f32x16 acc[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+    const bool mine = c < nchunk;
+    const uint32_t* eo = ent + ((size_t)i * nchunk_max + c) * (kBRows * kKMax);
+    const int* so = stage_off + ((size_t)i * nchunk_max + c) * (nst + 1);
+    uint4 breg[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      breg[q] = brow_ok ? *(const uint4*)(ysrc + q * 8) : uint4{0, 0, 0, 0};
+    for (int st = 0; st < nst; ++st) {
+      const int buf = st & 1;
+      // scatter this wave's nonzeros of the stage (rows of its half only)
+      int e0 = 0, e1 = 0;
+      if (mine) {
+        e0 = so[st];
+        e1 = so[st + 1];
+      }
+      for (int e = e0 + lane; e < e1; e += kWave) {
+        const uint32_t v = eo[e];
+        const int row = v & 127;
+        if ((row >> 6) == half) Aw[(row & 63) * kStage + ((v >> 7) & 63)] = (uint16_t)(v >> 16);
+      }
+      {
+        uint16_t* dst = Bs + (size_t)buf * kBTN * kStage + br * kStage + bh * 32;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *(uint4*)(dst + q * 8) = breg[q];
+      }
+      __syncthreads();  // B stage `buf` complete; the other buffer is free
+      if (st + 1 < nst) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          breg[q] = brow_ok ? *(const uint4*)(ysrc + (size_t)(st + 1) * kStage + q * 8)
+                            : uint4{0, 0, 0, 0};
+      }
+      if (e1 > e0) {
+        const uint16_t* Bb = Bs + (size_t)buf * kBTN * kStage;
+#pragma unroll
+        for (int kk = 0; kk < kStage / 16; ++kk) {
+          bf16x8 af[2], bfr[4];
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+            af[a] = *(const bf16x8*)(Aw + (32 * a + (lane & 31)) * kStage + 16 * kk + 8 * (lane >> 5));
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            bfr[b] = *(const bf16x8*)(Bb + (32 * b + (lane & 31)) * kStage + 16 * kk + 8 * (lane >> 5));
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+              acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+        }
+      }
+      // clear this wave's nonzeros again (after its own reads, in program order)
+      for (int e = e0 + lane; e < e1; e += kWave) {
+        const uint32_t v = eo[e];
+        const int row = v & 127;
+        if ((row >> 6) == half) Aw[(row & 63) * kStage + ((v >> 7) & 63)] = 0;
+      }
+    }
+    // epilogue: moments of this chunk's rows
+    if (mine) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int col = 32 * b + (lane & 31);
+        const int j = j0 + col;
+        float sy = 0.f, syy = 0.f, sp = 0.f, spp = 0.f, syp = 0.f;
+        if (j < n_tgt) {
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int row = kHalf * half + 32 * a + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+              const int t = lo + c * kBRows + row;
+              if (t < L) {
+                const float y = ts[(int64_t)t * ld + tgt0 + j];
+                const float p = acc[a][b][r];
+                sy += y;
+                syy = fmaf(y, y, syy);
+                sp += p;
+                spp = fmaf(p, p, spp);
+                syp = fmaf(y, p, syp);
+              }
+            }
+        }
+        mom[(0 * 4 + b) * kWave + lane] += sy;
+        mom[(1 * 4 + b) * kWave + lane] += syy;
+        mom[(2 * 4 + b) * kWave + lane] += sp;
+        mom[(3 * 4 + b) * kWave + lane] += spp;
+        mom[(4 * 4 + b) * kWave + lane] += syp;
+      }
+    }
+  }
+  __syncthreads();
+  // combine the two row halves (waves 2m, 2m+1) and lanes l, l+32 of the same column
+  if (!has || half != 0 || lane >= 32) return;
+  const double* m0 = mom;
+  const double* m1 = mom + 5 * 4 * kWave;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    double S[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const int o = (q * 4 + b) * kWave + lane;
+      S[q] = (m0[o] + m0[o + 32]) + (m1[o] + m1[o + 32]);
+    }
+    const int j = j0 + 32 * b + lane;
+    if (j < n_tgt) {
+      const double r = k > 0 ? pearson_from_moments((double)nrows, S[0], S[1], S[2], S[3], S[4])
+                             : __builtin_nan("");
+      rho[(size_t)i * n_tgt + j] = (float)r;
+      if (moments) {
+        double* mo = moments + ((size_t)i * n_tgt + j) * 3;
+        mo[0] = k > 0 ? S[2] : __builtin_nan("");
+        mo[1] = k > 0 ? S[3] : __builtin_nan("");
+        mo[2] = k > 0 ? S[4] : __builtin_nan("");
+      }
+    }
+  }
+}
+
+}  // namespace ccm
+
+extern "C" hipError_t ccm_launch_order(const int* lib_k, int n_lib, int* order, hipStream_t stream);
+
+extern "C" size_t ccm_bf16_lds_bytes() {
+  return 2 * (size_t)ccm::kBTN * ccm::kStage * 2 + 4 * (size_t)ccm::kHalf * ccm::kStage * 2 +
+         4 * 5 * 4 * (size_t)ccm::kWave * sizeof(double);
+}
+
+extern "C" hipError_t ccm_launch_crossmap_bf16(const float* ts, int64_t ld, int L, int tau, int tgt0,
+                                               int n_tgt, const int* nbr_idx, const float* nbr_w,
+                                               const int* lib_E, int n_lib, int k_max, float* rho,
+                                               double* moments, uint16_t* yt, uint32_t* ent,
+                                               int* stage_off, int* lib_k, int* order,
+                                               hipStream_t stream) {
+  if (n_lib == 0 || n_tgt == 0) return hipSuccess;
+  const int nst = (L + ccm::kStage - 1) / ccm::kStage;
+  const int Lpad = nst * ccm::kStage;
+  const int nchunk_max = (L + ccm::kBRows - 1) / ccm::kBRows;
+  hipLaunchKernelGGL(ccm::transpose_bf16_kernel, dim3((n_tgt + 63) / 64, Lpad / 64), dim3(256), 0,
+                     stream, ts, ld, L, tgt0, n_tgt, Lpad, yt);
+  hipLaunchKernelGGL(ccm::bf16_entries_kernel, dim3(nchunk_max, n_lib), dim3(ccm::kBRows), 0, stream,
+                     nbr_idx, nbr_w, lib_E, L, k_max, tau, nchunk_max, nst, ent, stage_off, lib_k);
+  hipError_t e = ccm_launch_order(lib_k, n_lib, order, stream);
+  if (e != hipSuccess) return e;
+  static bool attr = false;
+  if (!attr) {
+    e = hipFuncSetAttribute((const void*)ccm::gather_bf16_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)ccm_bf16_lds_bytes());
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(ccm::gather_bf16_kernel, dim3((n_tgt + ccm::kBTN - 1) / ccm::kBTN, (n_lib + 1) / 2),
+                     dim3(ccm::kBThreads), ccm_bf16_lds_bytes(), stream, ts, ld, L, tau, tgt0, n_tgt,
+                     Lpad, yt, ent, stage_off, order, lib_k, n_lib, nchunk_max, nst, rho, moments);
+  return hipGetLastError();
+}

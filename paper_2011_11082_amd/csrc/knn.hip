@@ -8,11 +8,13 @@
 // gfx950 design (not the paper's): one wavefront owns one query point.  Its 64 lanes
 // evaluate 64 candidate points at a time straight from an LDS copy of the series (the
 // embedding is never materialised), and the k best so far live in a sorted list spread
-// across lanes 0..k-1 (lane j holds the j-th nearest).  A candidate enters only if its d^2
-// beats the current k-th (one compare per lane, one ballot per chunk); the rare winners are
-// inserted one at a time, in ascending time order, by a DPP wave shift.  Because
-// candidates arrive in ascending time order, "strictly smaller d^2" is exactly the
-// (d^2, time index) order, so ties go to the lower index with no extra work.
+// across lanes 0..k-1 (lane j holds the j-th nearest by (d^2, time index)).  A candidate
+// can enter only if its d^2 does not exceed the current k-th (one compare per lane, one
+// ballot per chunk); the few survivors are inserted one at a time by a DPP wave shift.
+// The chunk around the query's own time is scanned first: for autocorrelated series its
+// points are close in state space, so the k-th distance tightens at once and later
+// chunks rarely insert.  The list order is lexicographic in (d^2, time index), so the
+// scan order does not change the result and ties go to the lower index.
 //
 // Selection distances follow one canonical FP32 operation sequence (lag 0 first; one rounding per
 // subtraction, product and sum; no fused multiply-add: this file is compiled with
@@ -30,32 +32,49 @@
 
 namespace ccm {
 
-// Insert candidate (v, sv) into the wave-distributed ascending list (ld, li).  Entries
-// equal to v stay ahead of it (they carry lower time indices).
+__device__ __forceinline__ bool lex_less(float a, int ia, float b, int ib) {
+  return a < b || (a == b && ia < ib);
+}
+
+// Insert candidate (v, sv) into the wave-distributed list (ld, li), ascending in
+// (d^2, time index).
 __device__ __forceinline__ void list_insert(float& ld, int& li, float v, int sv) {
   float pd = wave_shr1(ld, -INFINITY);
   int pi = wave_shr1(li, -1);
-  bool gt = ld > v;
-  bool gtp = pd > v;
+  bool gt = lex_less(v, sv, ld, li);
+  bool gtp = lex_less(v, sv, pd, pi);
   float nd = gtp ? pd : v;
   int ni = gtp ? pi : sv;
   ld = gt ? nd : ld;
   li = gt ? ni : li;
 }
 
-// Offer this chunk's candidates (cand = +inf where not admissible) to one list.
-// `k1` is k - 1, the lane holding the current k-th smallest.
-__device__ __forceinline__ void offer_chunk(float cand, int base, float& ld, int& li, float& thr,
-                                            int k1) {
-  uint64_t m = ballot(cand < thr);
+// Offer this chunk's candidates (cand = +inf where not admissible; s = time index) to one
+// list whose k-th entry (lane k1) is (thr, ithr).  The ballot pre-filters on d^2 <= thr;
+// the exact (d^2, index) test is made per survivor.
+__device__ __forceinline__ void offer_chunk(float cand, int s, float& ld, int& li, float& thr,
+                                            int& ithr, int k1) {
+  uint64_t m = ballot(cand <= thr);
   while (m) {
-    int src = __ffsll((unsigned long long)m) - 1;
-    float v = readlane(cand, src);
-    list_insert(ld, li, v, base + src);
-    thr = readlane(ld, k1);
+    const int src = __ffsll((unsigned long long)m) - 1;
+    const float v = readlane(cand, src);
+    const int sv = readlane(s, src);
+    if (lex_less(v, sv, thr, ithr)) {
+      list_insert(ld, li, v, sv);
+      thr = readlane(ld, k1);
+      ithr = readlane(li, k1);
+    }
     m &= (~0ull << src) << 1;
-    m &= ballot(cand < thr);
+    m &= ballot(cand <= thr);
   }
+}
+
+// First chunk base of the scan: the 64 points centred on the query, inside [clo, chi].
+__device__ __forceinline__ int window_base(int t, int clo, int chi) {
+  int b = t - 32;
+  if (b > chi - (kWave - 1)) b = chi - (kWave - 1);
+  if (b < clo) b = clo;
+  return b;
 }
 
 // Simplex weights of a finished list (lanes 0..k-1 hold neighbour n_j of query t).  The
@@ -121,15 +140,21 @@ __global__ __launch_bounds__(256) void knn_table_kernel(const float* __restrict_
     }
     float xq[kEMax];
 #pragma unroll
-    for (int e = 0; e < kEMax; ++e) xq[e] = (e < E) ? x[t - e * tau] : 0.0f;
+    for (int e = 0; e < kEMax; ++e)
+      xq[e] = __int_as_float(
+          __builtin_amdgcn_readfirstlane(__float_as_int((e < E) ? x[t - e * tau] : 0.0f)));
 
     float ldist = INFINITY;
     int lidx = -1;
     float thr = INFINITY;
-    for (int base = lo; base <= hi; base += kWave) {
-      const int s = base + lane;
-      const bool inr = s <= hi;
-      const int sc = inr ? s : hi;
+    int ithr = -1;
+    const int wb = window_base(t, lo, hi);
+    // pass -1: the window around t; then every chunk in order, skipping the window
+    for (int pass = -1, base = lo; base <= hi; base += (pass < 0 ? 0 : kWave), pass = 0) {
+      const int b = pass < 0 ? wb : base;
+      const int s = b + lane;
+      const bool inr = s <= hi && (pass < 0 || s < wb || s >= wb + kWave);
+      const int sc = s <= hi ? s : hi;
       float acc = 0.0f;
 #pragma unroll
       for (int e = 0; e < kEMax; ++e) {
@@ -139,7 +164,7 @@ __global__ __launch_bounds__(256) void knn_table_kernel(const float* __restrict_
         }
       }
       float cand = (inr && s != t) ? acc : INFINITY;
-      offer_chunk(cand, base, ldist, lidx, thr, k - 1);
+      offer_chunk(cand, s, ldist, lidx, thr, ithr, k - 1);
     }
     double usum;
     double u = list_weight64(x, t, lidx, E, tau, k, usum);
@@ -153,78 +178,99 @@ __global__ __launch_bounds__(256) void knn_table_kernel(const float* __restrict_
 }
 
 // ---------------------------------------------------------------------------------------
-// Simplex projection skill for E = E_min..E_max and optE, one workgroup per series.
-// LOO: Q_E = C_E = [(E-1)tau, L-1-Tp], query excluded.  HALF: C_E = [(E-1)tau, h-1-Tp],
-// Q_E = [h+(E-1)tau, L-1-Tp], h = L/2, no exclusion.
+// Simplex projection skill for E = E_lo..E_hi (at most kGroupE values), one workgroup per
+// (series, E group).  The squared distance is accumulated over lags 0..E_hi-1 once; each
+// E of the group keeps its own list.  LOO: Q_E = C_E = [(E-1)tau, L-1-Tp], query excluded.
+// HALF: C_E = [(E-1)tau, h-1-Tp], Q_E = [h+(E-1)tau, L-1-Tp], h = L/2, no exclusion.
+// Writes the FP64 skill of each E to rho64[series][E-1].
 // ---------------------------------------------------------------------------------------
 constexpr int kSimplexThreads = 512;
+constexpr int kGroupE = 10;
+
+struct EGroups {
+  int lo[3];
+  int hi[3];
+};
 
 __global__ __launch_bounds__(kSimplexThreads) void simplex_kernel(
-    const float* __restrict__ ts, int64_t ld, int L, const int* __restrict__ ids, int E_min,
-    int E_max, int tau, int Tp, int mode, int* __restrict__ optE, float* __restrict__ rho_E) {
+    const float* __restrict__ ts, int64_t ld, int L, const int* __restrict__ ids, EGroups groups,
+    int tau, int Tp, int mode, double* __restrict__ rho64) {
   extern __shared__ float x[];
-  __shared__ double wsum[kSimplexThreads / kWave][kEMax][5];
+  __shared__ double wsum[kSimplexThreads / kWave][kGroupE][5];
   const int sid = ids[blockIdx.x];
+  const int E_lo = groups.lo[blockIdx.y];
+  const int E_hi = groups.hi[blockIdx.y];
   for (int t = threadIdx.x; t < L; t += blockDim.x) x[t] = ts[(int64_t)t * ld + sid];
   __syncthreads();
 
   const int lane = lane_id();
-  const int wave = threadIdx.x / kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int nw = blockDim.x / kWave;
   const bool half = mode == 1;
   const int h = L / 2;
   const int qbase = half ? h : 0;
   const int chi = half ? h - 1 - Tp : L - 1 - Tp;     // last candidate
-  const int clo = (E_min - 1) * tau;                   // first candidate over all E
-  const int qlo = qbase + (E_min - 1) * tau;
+  const int clo = (E_lo - 1) * tau;                    // first candidate over the group
+  const int qlo = qbase + (E_lo - 1) * tau;
   const int qhi = L - 1 - Tp;
 
-  // lane e holds the five FP64 moment sums of E = e + 1
+  // lane g holds the five FP64 moment sums of E = E_lo + g
   double m_o = 0.0, m_oo = 0.0, m_p = 0.0, m_pp = 0.0, m_op = 0.0;
 
   for (int t = qlo + wave; t <= qhi; t += nw) {
     float xq[kEMax];
 #pragma unroll
-    for (int e = 0; e < kEMax; ++e) xq[e] = (e < E_max && t - e * tau >= 0) ? x[t - e * tau] : 0.0f;
-    float ldist[kEMax];
-    int lidx[kEMax];
-    float thr[kEMax];
+    for (int e = 0; e < kEMax; ++e)
+      xq[e] = __int_as_float(__builtin_amdgcn_readfirstlane(
+          __float_as_int((e < E_hi && t - e * tau >= 0) ? x[t - e * tau] : 0.0f)));
+    float ldist[kGroupE];
+    int lidx[kGroupE];
+    float thr[kGroupE];
+    int ithr[kGroupE];
 #pragma unroll
-    for (int e = 0; e < kEMax; ++e) {
-      ldist[e] = INFINITY;
-      lidx[e] = -1;
-      thr[e] = INFINITY;
+    for (int g = 0; g < kGroupE; ++g) {
+      ldist[g] = INFINITY;
+      lidx[g] = -1;
+      thr[g] = INFINITY;
+      ithr[g] = -1;
     }
-    for (int base = clo; base <= chi; base += kWave) {
-      const int s = base + lane;
-      const bool inr = s <= chi;
-      const int sc = inr ? s : chi;
+    // the window of candidates around t first (HALF mode: candidates are in the other
+    // half, so the window clamps to its end), then every chunk in order
+    const int wb = window_base(t, clo, chi);
+    for (int pass = -1, base = clo; base <= chi; base += (pass < 0 ? 0 : kWave), pass = 0) {
+      const int b = pass < 0 ? wb : base;
+      const int s = b + lane;
+      const bool inr = s <= chi && (pass < 0 || s < wb || s >= wb + kWave);
+      const int sc = s <= chi ? s : chi;
       float acc = 0.0f;
 #pragma unroll
       for (int e = 0; e < kEMax; ++e) {
-        if (e < E_max) {
+        if (e < E_hi) {
           const int xi = sc - e * tau;
           float df = xq[e] - x[xi > 0 ? xi : 0];
           acc = acc + df * df;
           const int E = e + 1;
-          if (E >= E_min && t >= qbase + (E - 1) * tau) {
+          const int g = E - E_lo;
+          if (g >= 0 && t >= qbase + (E - 1) * tau) {
             const bool adm = inr && sc >= (E - 1) * tau && (half || s != t);
             float cand = adm ? acc : INFINITY;
-            offer_chunk(cand, base, ldist[e], lidx[e], thr[e], E);
+#pragma unroll
+            for (int gg = 0; gg < kGroupE; ++gg)
+              if (gg == g) offer_chunk(cand, s, ldist[gg], lidx[gg], thr[gg], ithr[gg], E);
           }
         }
       }
     }
     const float obs = x[t + Tp];
 #pragma unroll
-    for (int e = 0; e < kEMax; ++e) {
-      const int E = e + 1;
-      if (e < E_max && E >= E_min && t >= qbase + (E - 1) * tau) {
+    for (int g = 0; g < kGroupE; ++g) {
+      const int E = E_lo + g;
+      if (E <= E_hi && t >= qbase + (E - 1) * tau) {
         double usum;
-        double u = list_weight64(x, t, lidx[e], E, tau, E + 1, usum);
-        double f = (lane <= E && lidx[e] >= 0) ? (double)x[lidx[e] + Tp] : 0.0;
+        double u = list_weight64(x, t, lidx[g], E, tau, E + 1, usum);
+        double f = (lane <= E && lidx[g] >= 0) ? (double)x[lidx[g] + Tp] : 0.0;
         double pred = wave_sum(u * f) / usum;
-        if (lane == e) {
+        if (lane == g) {
           double o = obs, p = pred;
           m_o += o;
           m_oo += o * o;
@@ -235,7 +281,7 @@ __global__ __launch_bounds__(kSimplexThreads) void simplex_kernel(
       }
     }
   }
-  if (lane < kEMax) {
+  if (lane < kGroupE) {
     wsum[wave][lane][0] = m_o;
     wsum[wave][lane][1] = m_oo;
     wsum[wave][lane][2] = m_p;
@@ -243,27 +289,41 @@ __global__ __launch_bounds__(kSimplexThreads) void simplex_kernel(
     wsum[wave][lane][4] = m_op;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const int nE = E_max - E_min + 1;
-    double best = 0.0;
-    int bestE = E_min;
-    bool have = false;
-    for (int E = E_min; E <= E_max; ++E) {
-      double s[5] = {0, 0, 0, 0, 0};
+  if (threadIdx.x < kGroupE) {
+    const int g = threadIdx.x;
+    const int E = E_lo + g;
+    if (E <= E_hi) {
+      double sm[5] = {0, 0, 0, 0, 0};
       for (int w = 0; w < nw; ++w)
-        for (int c = 0; c < 5; ++c) s[c] += wsum[w][E - 1][c];
+        for (int c = 0; c < 5; ++c) sm[c] += wsum[w][g][c];
       const int qfirst = qbase + (E - 1) * tau;
       const double n = (double)(qhi - qfirst + 1);
-      double r = n > 0 ? pearson_from_moments(n, s[0], s[1], s[2], s[3], s[4]) : __builtin_nan("");
-      if (rho_E) rho_E[(size_t)blockIdx.x * nE + (E - E_min)] = (float)r;
-      if (r == r && (!have || r > best)) {
-        best = r;
-        bestE = E;
-        have = true;
-      }
+      rho64[(size_t)blockIdx.x * kEMax + (E - 1)] =
+          n > 0 ? pearson_from_moments(n, sm[0], sm[1], sm[2], sm[3], sm[4]) : __builtin_nan("");
     }
-    optE[blockIdx.x] = bestE;
   }
+}
+
+// optE = smallest E reaching the largest non-NaN skill (E_min if all are NaN).
+__global__ void simplex_finalize_kernel(const double* __restrict__ rho64, int n, int E_min,
+                                        int E_max, int* __restrict__ optE,
+                                        float* __restrict__ rho_E) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int nE = E_max - E_min + 1;
+  double best = 0.0;
+  int bestE = E_min;
+  bool have = false;
+  for (int E = E_min; E <= E_max; ++E) {
+    const double r = rho64[(size_t)i * kEMax + (E - 1)];
+    if (rho_E) rho_E[(size_t)i * nE + (E - E_min)] = (float)r;
+    if (r == r && (!have || r > best)) {
+      best = r;
+      bestE = E;
+      have = true;
+    }
+  }
+  optE[i] = bestE;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -301,11 +361,28 @@ extern "C" hipError_t ccm_launch_knn(const float* ts, int64_t ld, int L, const i
 
 extern "C" hipError_t ccm_launch_simplex(const float* ts, int64_t ld, int L, const int* ids, int n,
                                          int E_min, int E_max, int tau, int Tp, int mode,
-                                         int* optE, float* rho_E, hipStream_t stream) {
+                                         int* optE, float* rho_E, double* rho64,
+                                         hipStream_t stream) {
   if (n == 0) return hipSuccess;
+  // E groups of about equal work (lags grow with E, and so do list sizes)
+  static const int kLo[3] = {1, 11, 17};
+  static const int kHi[3] = {10, 16, 20};
+  ccm::EGroups grp;
+  int ng = 0;
+  for (int g = 0; g < 3; ++g) {
+    int lo = kLo[g] > E_min ? kLo[g] : E_min;
+    int hi = kHi[g] < E_max ? kHi[g] : E_max;
+    if (lo <= hi) {
+      grp.lo[ng] = lo;
+      grp.hi[ng] = hi;
+      ++ng;
+    }
+  }
   size_t lds = (size_t)L * sizeof(float);
-  hipLaunchKernelGGL(ccm::simplex_kernel, dim3(n), dim3(ccm::kSimplexThreads), lds, stream, ts, ld,
-                     L, ids, E_min, E_max, tau, Tp, mode, optE, rho_E);
+  hipLaunchKernelGGL(ccm::simplex_kernel, dim3(n, ng), dim3(ccm::kSimplexThreads), lds, stream, ts,
+                     ld, L, ids, grp, tau, Tp, mode, rho64);
+  hipLaunchKernelGGL(ccm::simplex_finalize_kernel, dim3((n + 255) / 256), dim3(256), 0, stream,
+                     rho64, n, E_min, E_max, optE, rho_E);
   return hipGetLastError();
 }
 

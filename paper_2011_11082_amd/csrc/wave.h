@@ -27,14 +27,15 @@ __device__ __forceinline__ int wave_shr1(int v, int old) {
   return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xF, 0xF, false);
 }
 
-// DPP quad_perm broadcast: every lane of a quad receives lane M of that quad.
+// DPP quad_perm broadcast: every lane of a quad receives lane M of that quad (every source
+// lane exists, so no "old" value is needed).
 template <int M>
 __device__ __forceinline__ int quad_bcast(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, M * 0x55, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(v, M * 0x55, 0xF, 0xF, true);
 }
 template <int M>
 __device__ __forceinline__ float quad_bcast(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), M * 0x55, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), M * 0x55, 0xF, 0xF, true));
 }
 
 // Sum over all 64 lanes (result in every lane).

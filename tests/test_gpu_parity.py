@@ -209,3 +209,47 @@ def test_crossmap_nan_for_constant_target_and_bad_library(ccm):
     idx_o, w_o, _ = O.knn(ts, [0, 1], lib_E[:2], 1, 0, 4)
     rho_o = O.crossmap_rho(ts, idx_o, w_o, lib_E[:2], 1, 0, 20)
     _check_rho(rho[:2], rho_o, "small")
+
+
+# ---------------------------------------------------------------------------------------
+BF16_TOL = 5e-3
+
+
+def test_crossmap_bf16_logistic64(ccm):
+    w = synth.make("logistic64")
+    ts = w.panel
+    oE = (np.arange(64) % 7 + 2).astype(np.int32)
+    _say("crossmap BF16 logistic64 64x64")
+    idx, wt, _ = ccm.knn(_cuda(ts), np.arange(64), oE, k_max=11)
+    rho = ccm.crossmap_rho(_cuda(ts), idx, wt, oE, precision=ccm.PRECISION_BF16).cpu().numpy()
+    rho_o, _, _, _ = O.ccm_block(ts, np.arange(64), oE, 1, 0, 64, k_max=11)
+    _check_rho(rho, rho_o, "logistic64 BF16", tol=BF16_TOL)
+
+
+def test_crossmap_bf16_ratenet_ragged(ccm):
+    w = synth.make("ratenet1024")
+    ts = w.panel
+    lib_ids = np.arange(3, 1024, 51, dtype=np.int32)  # 21 libraries (odd count)
+    lib_E = (np.arange(21) * 3 % 20 + 1).astype(np.int32)
+    tgt0, n_tgt = 5, 1000  # ragged last 128-target tile
+    _say("crossmap BF16 ratenet1024 21 libs x 1000 targets")
+    idx, wt, _ = ccm.knn(_cuda(ts), lib_ids, lib_E, k_max=21)
+    rho, mom = ccm.crossmap_rho(_cuda(ts), idx, wt, lib_E, tgt0=tgt0, n_tgt=n_tgt,
+                                precision=ccm.PRECISION_BF16, want_moments=True)
+    idx_o, w_o, _ = O.knn(ts, lib_ids, lib_E, 1, 0, 21)
+    rho_o = O.crossmap_rho(ts, idx_o, w_o, lib_E, 1, tgt0, n_tgt)
+    _check_rho(rho.cpu().numpy(), rho_o, "ratenet1024 BF16", tol=BF16_TOL)
+    rho32 = ccm.crossmap_rho(_cuda(ts), idx, wt, lib_E, tgt0=tgt0, n_tgt=n_tgt).cpu().numpy()
+    _check_rho(rho32, rho_o, "ratenet1024 FP32 (same tables)")
+
+
+def test_crossmap_bf16_nan_cases(ccm):
+    rng = np.random.default_rng(9)
+    ts = rng.standard_normal((120, 20)).astype(np.float32)
+    ts[:, 4] = 2.0
+    lib_E = np.array([3, 2, 0], dtype=np.int32)
+    _say("crossmap BF16 NaN cases")
+    idx, wt, _ = ccm.knn(_cuda(ts), [0, 1, 2], lib_E, k_max=4)
+    rho = ccm.crossmap_rho(_cuda(ts), idx, wt, lib_E, precision=ccm.PRECISION_BF16).cpu().numpy()
+    assert np.all(np.isnan(rho[:, 4])) and np.all(np.isnan(rho[2]))
+    assert not np.any(np.isnan(np.delete(rho[:2], 4, 1)))
