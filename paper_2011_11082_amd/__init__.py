@@ -232,3 +232,48 @@ def crossmap_rho_backward(ts, lib_ts, nbr_idx, nbr_w, lib_E, pair_lib, pair_tgt,
                                          _ptr(pair_tgt), _ptr(grad_rho), n_pairs, _ptr(grad_ts),
                                          _ptr(grad_lib), _ptr(ws), need, _stream()))
     return grad_ts, grad_lib
+
+
+class CrossMapRho(torch.autograd.Function):
+    """rho[i][j] = cross-map skill of library series X[i] for target column Y[:, j].
+
+    X: [n_lib][L] library series; Y: [L][N] time-major target panel; lib_E: E of each
+    library.  Forward builds one table per library (ccm_knn, Tp = 0) and runs
+    ccm_crossmap_rho.  Backward runs the hand-written adjoint (ccm_crossmap_rho_backward)
+    with the neighbour sets held fixed: d rho / d Y through the observed and looked-up
+    target values, d rho / d X through the distances and weights.  The adjoint is that of
+    the FP32 form, whichever precision the forward used.
+    """
+
+    @staticmethod
+    def forward(ctx, X, Y, lib_E, tau=1, precision=PRECISION_FP32):
+        Xd = X.detach().contiguous()
+        Yd = Y.detach()
+        lib_E = _i32(lib_E, Xd.device)
+        n_lib, L = Xd.shape
+        k_max = int(lib_E.max().item()) + 1 if n_lib else 2
+        panel = Xd.t().contiguous()
+        ids = torch.arange(n_lib, dtype=torch.int32, device=Xd.device)
+        idx, w, _ = knn(panel, ids, lib_E, tau, 0, max(k_max, 2), want_d2=False)
+        rho = crossmap_rho(Yd, idx, w, lib_E, tau, 0, int(Yd.shape[1]), precision)
+        ctx.save_for_backward(Xd, Yd, idx, w, lib_E)
+        ctx.tau = tau
+        return rho
+
+    @staticmethod
+    def backward(ctx, grad_rho):
+        X, Y, idx, w, lib_E = ctx.saved_tensors
+        g = grad_rho.to(torch.float32)
+        nz = torch.nonzero(g != 0)
+        pair_lib = nz[:, 0].to(torch.int32)
+        pair_tgt = nz[:, 1].to(torch.int32)
+        gvals = g[nz[:, 0], nz[:, 1]].contiguous()
+        gts = torch.zeros(Y.shape, dtype=torch.float32, device=Y.device)
+        glib = torch.zeros(X.shape, dtype=torch.float32, device=X.device)
+        crossmap_rho_backward(Y, X, idx, w, lib_E, pair_lib, pair_tgt, gvals, ctx.tau, gts, glib)
+        return glib, gts, None, None, None
+
+
+def crossmap_rho_autograd(X, Y, lib_E, tau: int = 1, precision: int = PRECISION_FP32):
+    """Differentiable rho block: see ``CrossMapRho``."""
+    return CrossMapRho.apply(X, Y, lib_E, tau, precision)

@@ -25,6 +25,7 @@ SOURCES = {
     "knn.hip": ["-ffp-contract=off"],
     "crossmap.hip": [],
     "crossmap_bf16.hip": [],
+    "adjoint.hip": [],
     "ccm_abi.cpp": ["-x", "hip"],
 }
 

@@ -1,0 +1,282 @@
+// Adjoint of the cross-map: gradient of loss = sum_p g_p * rho[lib_p][tgt_p] with every
+// neighbour set held fixed (not in the paper; the forward is Sec. III-B, Alg. 2 / Alg. 5
+// with corrcoef, and the weights of Sec. III-A).
+//
+// For one pair (library i, target column j) with rows t in Q = [(E-1)tau, L-1]:
+//   yhat(t) = sum_m w[t,m] y(n_m(t));  rho = c / sqrt(a b) with centred sums
+//   a = sum (y-ybar)^2, b = sum (yhat-pbar)^2, c = sum (y-ybar)(yhat-pbar)
+//   H(t)  = g drho/dyhat(t) = g [ (y(t)-ybar)/sqrt(ab) - rho (yhat(t)-pbar)/b ]
+//   Gy(t) = g drho/dy(t)|obs = g [ (yhat(t)-pbar)/sqrt(ab) - rho (y(t)-ybar)/a ]
+//   target:  dL/dy(s) = Gy(s) [s in Q] + sum_{(t,m): n_m(t) = s} w[t,m] H(t)
+//   weights: wbar[t,m] = H(t) y(n_m(t));  w = u / S, u_m = exp(-d_m / d_1)
+//            ubar_m = (wbar_m - sum_l wbar_l w_l) / S
+//            dbar_m = -ubar_m u_m / d_1 (m >= 2);  dbar_1 = sum_{m>=2} ubar_m u_m d_m / d_1^2
+//            (u_1 = e^-1 does not depend on x; zero distances contribute nothing)
+//   library: d_m = ||v(t) - v(n_m)||, so coef = dbar_m / d_m gives
+//            dL/dx(t - e tau) += coef (x(t-e tau) - x(n_m - e tau))
+//            dL/dx(n_m - e tau) -= coef (x(t-e tau) - x(n_m - e tau))
+//
+// gfx950 design: no atomics, fixed summation order (deterministic results).  Kernel 1:
+// one workgroup per pair recomputes yhat and the FP64 Pearson pieces and stores H, Gy.
+// Kernel 2: one thread per (pair, t) turns wbar into distance coefficients (distances
+// recomputed in FP64 from the library series).  Kernel 3: one thread per (pair, s) gathers
+// everything that lands on time s by scanning the pair's table (the transpose of the
+// neighbour relation, without building it).  Kernel 4: one thread per s adds the pairs'
+// contributions in pair order into the target and library gradients.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "wave.h"
+
+namespace ccm {
+
+constexpr int kBwThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = lane_id();
+  const int wave = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (int)(blockDim.x / kWave); ++w) s += red[w];
+  return s;
+}
+
+__global__ __launch_bounds__(kBwThreads) void bw_pair_kernel(
+    const float* __restrict__ ts, int64_t ld, int L, const int* __restrict__ nbr_idx,
+    const float* __restrict__ nbr_w, const int* __restrict__ lib_E, int n_lib, int k_max, int tau,
+    const int* __restrict__ pair_lib, const int* __restrict__ pair_tgt,
+    const float* __restrict__ grad_rho, float* __restrict__ yhat, float* __restrict__ H,
+    float* __restrict__ Gy, int* __restrict__ pair_ok) {
+  __shared__ double red[kBwThreads / kWave];
+  const int p = blockIdx.x;
+  const int i = pair_lib[p];
+  const int j = pair_tgt[p];
+  const int E = (i >= 0 && i < n_lib) ? lib_E[i] : 0;
+  const int k = E + 1;
+  const int lo = (E - 1) * tau;
+  bool ok = i >= 0 && i < n_lib && j >= 0 && j < ld && E >= 1 && E <= kEMax && k <= k_max &&
+            L - lo >= k + 1;
+  if (ok) ok = nbr_idx[((size_t)i * L + lo) * k_max] >= 0;
+  float* yh = yhat + (size_t)p * L;
+  float* hp = H + (size_t)p * L;
+  float* gp = Gy + (size_t)p * L;
+  if (!ok) {
+    for (int t = threadIdx.x; t < L; t += blockDim.x) hp[t] = gp[t] = yh[t] = 0.0f;
+    if (threadIdx.x == 0) pair_ok[p] = 0;
+    return;
+  }
+  double sy = 0.0, sp = 0.0;
+  for (int t = threadIdx.x; t < L; t += blockDim.x) {
+    float v = 0.0f;
+    if (t >= lo) {
+      const int* ri = nbr_idx + ((size_t)i * L + t) * k_max;
+      const float* rw = nbr_w + ((size_t)i * L + t) * k_max;
+      for (int m = 0; m < k; ++m) v = fmaf(rw[m], ts[(int64_t)ri[m] * ld + j], v);
+      sy += ts[(int64_t)t * ld + j];
+      sp += v;
+    }
+    yh[t] = v;
+  }
+  const double n = (double)(L - lo);
+  const double ybar = block_sum(sy, red) / n;
+  const double pbar = block_sum(sp, red) / n;
+  double a = 0.0, b = 0.0, c = 0.0, ay = 0.0, bp = 0.0;
+  for (int t = lo + threadIdx.x; t < L; t += blockDim.x) {
+    const double y = ts[(int64_t)t * ld + j];
+    const double q = yh[t];
+    a += (y - ybar) * (y - ybar);
+    b += (q - pbar) * (q - pbar);
+    c += (y - ybar) * (q - pbar);
+    ay += y * y;
+    bp += q * q;
+  }
+  a = block_sum(a, red);
+  b = block_sum(b, red);
+  c = block_sum(c, red);
+  ay = block_sum(ay, red);
+  bp = block_sum(bp, red);
+  const bool good = a > 1e-10 * ay && b > 1e-10 * bp;
+  const double g = grad_rho[p];
+  const double sab = sqrt(a * b);
+  const double rho = good ? c / sab : 0.0;
+  for (int t = threadIdx.x; t < L; t += blockDim.x) {
+    double h = 0.0, gy = 0.0;
+    if (good && t >= lo) {
+      const double dy = (double)ts[(int64_t)t * ld + j] - ybar;
+      const double dq = (double)yh[t] - pbar;
+      h = g * (dy / sab - rho * dq / b);
+      gy = g * (dq / sab - rho * dy / a);
+    }
+    hp[t] = (float)h;
+    gp[t] = (float)gy;
+  }
+  if (threadIdx.x == 0) pair_ok[p] = good ? 1 : 0;
+}
+
+// coef[p][t][m] = dbar_m / d_m (0 for zero distances), one thread per (pair, t).
+__global__ __launch_bounds__(256) void bw_coef_kernel(
+    const float* __restrict__ ts, int64_t ld, int L, const float* __restrict__ lib_ts,
+    const int* __restrict__ nbr_idx, const int* __restrict__ lib_E, int k_max, int tau,
+    const int* __restrict__ pair_lib, const int* __restrict__ pair_tgt, int n_pairs,
+    const float* __restrict__ H, const int* __restrict__ pair_ok, float* __restrict__ coef) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)n_pairs * L) return;
+  const int p = (int)(g / L);
+  const int t = (int)(g % L);
+  float* co = coef + ((size_t)p * L + t) * k_max;
+  const int i = pair_lib[p];
+  const int E = pair_ok[p] ? lib_E[i] : 0;
+  const int k = E + 1;
+  const int lo = (E - 1) * tau;
+  if (!pair_ok[p] || t < lo) {
+    for (int m = 0; m < k_max; ++m) co[m] = 0.0f;
+    return;
+  }
+  const int j = pair_tgt[p];
+  const float* x = lib_ts + (size_t)i * L;
+  const int* ri = nbr_idx + ((size_t)i * L + t) * k_max;
+  const double h = H[(size_t)p * L + t];
+  double d[kKMax], u[kKMax], wb[kKMax];
+  for (int m = 0; m < k; ++m) {
+    const int nb = ri[m];
+    double dd = 0.0;
+    for (int e = 0; e < E; ++e) {
+      const double df = (double)x[t - e * tau] - (double)x[nb - e * tau];
+      dd += df * df;
+    }
+    d[m] = sqrt(dd);
+    wb[m] = h * (double)ts[(int64_t)nb * ld + j];
+  }
+  const double d1 = d[0];
+  double S = 0.0;
+  for (int m = 0; m < k; ++m) {
+    u[m] = d1 > 0.0 ? exp(-d[m] / d1) : (d[m] == 0.0 ? 1.0 : 0.0);
+    S += u[m];
+  }
+  double sw = 0.0;
+  for (int m = 0; m < k; ++m) sw += wb[m] * (u[m] / S);
+  double dbar1 = 0.0;
+  for (int m = 0; m < k_max; ++m) {
+    double cm = 0.0;
+    if (m >= 1 && m < k && d1 > 0.0 && d[m] > 0.0) {
+      const double ub = (wb[m] - sw) / S;
+      const double db = -ub * u[m] / d1;
+      dbar1 += ub * u[m] * d[m] / (d1 * d1);
+      cm = db / d[m];
+    }
+    if (m >= 1) co[m] = (float)cm;
+  }
+  co[0] = d1 > 0.0 ? (float)(dbar1 / d1) : 0.0f;
+}
+
+// Contributions of pair p to time s: target (tc) and library (lc).  One thread per (p, s).
+__global__ __launch_bounds__(256) void bw_scatter_kernel(
+    const float* __restrict__ ts, int64_t ld, int L, const float* __restrict__ lib_ts,
+    const int* __restrict__ nbr_idx, const float* __restrict__ nbr_w, const int* __restrict__ lib_E,
+    int k_max, int tau, const int* __restrict__ pair_lib, int n_pairs, const float* __restrict__ H,
+    const float* __restrict__ Gy, const int* __restrict__ pair_ok, const float* __restrict__ coef,
+    float* __restrict__ tc, float* __restrict__ lc) {
+  const int p = blockIdx.y;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= L) return;
+  float* tco = tc + (size_t)p * L;
+  float* lco = lc + (size_t)p * L;
+  if (!pair_ok[p]) {
+    tco[s] = 0.0f;
+    lco[s] = 0.0f;
+    return;
+  }
+  const int i = pair_lib[p];
+  const int E = lib_E[i];
+  const int k = E + 1;
+  const int lo = (E - 1) * tau;
+  const float* x = lib_ts + (size_t)i * L;
+  const float* hp = H + (size_t)p * L;
+  const float* co = coef + (size_t)p * L * k_max;
+  const double xs = x[s];
+  double T = s >= lo ? (double)Gy[(size_t)p * L + s] : 0.0;
+  double Lb = 0.0;
+  // s as a lag coordinate of query t = s + e tau
+  for (int e = 0; e < E; ++e) {
+    const int t = s + e * tau;
+    if (t < lo || t >= L) continue;
+    const int* ri = nbr_idx + ((size_t)i * L + t) * k_max;
+    for (int m = 0; m < k; ++m) Lb += (double)co[(size_t)t * k_max + m] * (xs - (double)x[ri[m] - e * tau]);
+  }
+  // s as the neighbour (target gather) or a lag coordinate of a neighbour
+  const int span = (E - 1) * tau;
+  for (int t = lo; t < L; ++t) {
+    const int* ri = nbr_idx + ((size_t)i * L + t) * k_max;
+    const float* rw = nbr_w + ((size_t)i * L + t) * k_max;
+    for (int m = 0; m < k; ++m) {
+      const int dlt = ri[m] - s;
+      if (dlt < 0 || dlt > span) continue;
+      if (dlt == 0) T += (double)rw[m] * (double)hp[t];
+      if (dlt % tau == 0) {
+        const int e = dlt / tau;
+        Lb -= (double)co[(size_t)t * k_max + m] * ((double)x[t - e * tau] - xs);
+      }
+    }
+  }
+  tco[s] = (float)T;
+  lco[s] = (float)Lb;
+}
+
+// grad_ts[s][tgt_p] += tc[p][s], grad_lib[lib_p][s] += lc[p][s], pairs in order.
+__global__ void bw_reduce_kernel(int64_t ld, int L, const int* __restrict__ pair_lib,
+                                 const int* __restrict__ pair_tgt, int n_pairs,
+                                 const int* __restrict__ pair_ok, const float* __restrict__ tc,
+                                 const float* __restrict__ lc, float* __restrict__ grad_ts,
+                                 float* __restrict__ grad_lib) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= L) return;
+  for (int p = 0; p < n_pairs; ++p) {
+    if (!pair_ok[p]) continue;
+    if (grad_ts) grad_ts[(int64_t)s * ld + pair_tgt[p]] += tc[(size_t)p * L + s];
+    if (grad_lib) grad_lib[(size_t)pair_lib[p] * L + s] += lc[(size_t)p * L + s];
+  }
+}
+
+}  // namespace ccm
+
+extern "C" size_t ccm_backward_ws_bytes(int L, int n_pairs, int k_max) {
+  // yhat, H, Gy, tc, lc: [P][L] floats; coef: [P][L][k_max] floats; pair_ok: [P] ints
+  const size_t a = (size_t)n_pairs * L * 4;
+  return 5 * ((a + 255) & ~(size_t)255) + (((size_t)n_pairs * L * k_max * 4 + 255) & ~(size_t)255) +
+         (((size_t)n_pairs * 4 + 255) & ~(size_t)255);
+}
+
+extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, const float* lib_ts,
+                                          const int* nbr_idx, const float* nbr_w, const int* lib_E,
+                                          int n_lib, int k_max, int tau, const int* pair_lib,
+                                          const int* pair_tgt, const float* grad_rho, int n_pairs,
+                                          float* grad_ts, float* grad_lib, void* ws,
+                                          hipStream_t stream) {
+  if (n_pairs == 0) return hipSuccess;
+  const size_t a = (((size_t)n_pairs * L * 4) + 255) & ~(size_t)255;
+  char* base = (char*)ws;
+  float* yhat = (float*)base;
+  float* H = (float*)(base + a);
+  float* Gy = (float*)(base + 2 * a);
+  float* tc = (float*)(base + 3 * a);
+  float* lc = (float*)(base + 4 * a);
+  float* coef = (float*)(base + 5 * a);
+  int* pair_ok = (int*)(base + 5 * a + ((((size_t)n_pairs * L * k_max * 4) + 255) & ~(size_t)255));
+  hipLaunchKernelGGL(ccm::bw_pair_kernel, dim3(n_pairs), dim3(ccm::kBwThreads), 0, stream, ts, ld, L,
+                     nbr_idx, nbr_w, lib_E, n_lib, k_max, tau, pair_lib, pair_tgt, grad_rho, yhat, H,
+                     Gy, pair_ok);
+  const int64_t rows = (int64_t)n_pairs * L;
+  hipLaunchKernelGGL(ccm::bw_coef_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, stream,
+                     ts, ld, L, lib_ts, nbr_idx, lib_E, k_max, tau, pair_lib, pair_tgt, n_pairs, H,
+                     pair_ok, coef);
+  hipLaunchKernelGGL(ccm::bw_scatter_kernel, dim3((L + 255) / 256, n_pairs), dim3(256), 0, stream, ts,
+                     ld, L, lib_ts, nbr_idx, nbr_w, lib_E, k_max, tau, pair_lib, n_pairs, H, Gy,
+                     pair_ok, coef, tc, lc);
+  hipLaunchKernelGGL(ccm::bw_reduce_kernel, dim3((L + 255) / 256), dim3(256), 0, stream, ld, L,
+                     pair_lib, pair_tgt, n_pairs, pair_ok, tc, lc, grad_ts, grad_lib);
+  return hipGetLastError();
+}

@@ -31,6 +31,12 @@ hipError_t ccm_launch_crossmap_bf16(const float* ts, int64_t ld, int L, int tau,
                                     int n_lib, int k_max, float* rho, double* moments, uint16_t* yt,
                                     uint32_t* ent, int* stage_off, int* lib_k, int* order,
                                     hipStream_t stream);
+size_t ccm_backward_ws_bytes(int L, int n_pairs, int k_max);
+hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, const float* lib_ts,
+                               const int* nbr_idx, const float* nbr_w, const int* lib_E, int n_lib,
+                               int k_max, int tau, const int* pair_lib, const int* pair_tgt,
+                               const float* grad_rho, int n_pairs, float* grad_ts, float* grad_lib,
+                               void* ws, hipStream_t stream);
 }
 
 namespace {
@@ -135,8 +141,8 @@ ccm_status ccm_workspace_size(int32_t op, int32_t L, int32_t n_lib, int32_t n_tg
     case CCM_OP_CROSSMAP_BF16:
       *bytes = bf16_ws(L, n_lib, n_tgt).total;
       return CCM_OK;
-    case CCM_OP_CROSSMAP_BACKWARD:
-      *bytes = 0;
+    case CCM_OP_CROSSMAP_BACKWARD:  // n_tgt = number of pairs
+      *bytes = ccm_backward_ws_bytes(L, n_tgt, k_max);
       return CCM_OK;
     default:
       return fail(CCM_EINVAL, "ccm_workspace_size", "unknown op");
@@ -247,10 +253,20 @@ ccm_status ccm_crossmap_rho_backward(const float* ts, int64_t ld, int32_t L, con
                                      int32_t tau, const int32_t* pair_lib, const int32_t* pair_tgt,
                                      const float* grad_rho, int32_t n_pairs, float* grad_ts,
                                      float* grad_lib, void* ws, size_t ws_bytes, void* stream) {
-  (void)ts; (void)ld; (void)L; (void)lib_ts; (void)nbr_idx; (void)nbr_w; (void)lib_E; (void)n_lib;
-  (void)k_max; (void)tau; (void)pair_lib; (void)pair_tgt; (void)grad_rho; (void)n_pairs;
-  (void)grad_ts; (void)grad_lib; (void)ws; (void)ws_bytes; (void)stream;
-  return fail(CCM_ENOTSUP, "ccm_crossmap_rho_backward", "not built yet");
+  const char* fn = "ccm_crossmap_rho_backward";
+  ccm_status st = CCM_OK;
+  if (!check_series(fn, &st, ts, ld, L, tau)) return st;
+  if (n_lib < 0 || n_pairs < 0) return fail(CCM_EINVAL, fn, "negative size");
+  if (k_max < 2 || k_max > CCM_K_MAX) return fail(CCM_EINVAL, fn, "k_max outside [2, CCM_K_MAX]");
+  if (n_pairs == 0) return CCM_OK;
+  if (!lib_ts || !nbr_idx || !nbr_w || !lib_E || !pair_lib || !pair_tgt || !grad_rho)
+    return fail(CCM_EINVAL, fn, "NULL array argument");
+  if (!grad_ts && !grad_lib) return fail(CCM_EINVAL, fn, "both gradients are NULL");
+  const size_t need = ccm_backward_ws_bytes(L, n_pairs, k_max);
+  if (!ws || ws_bytes < need) return fail(CCM_EWORKSPACE, fn, "workspace too small");
+  return device_status(fn, ccm_launch_backward(ts, ld, L, lib_ts, nbr_idx, nbr_w, lib_E, n_lib,
+                                               k_max, tau, pair_lib, pair_tgt, grad_rho, n_pairs,
+                                               grad_ts, grad_lib, ws, (hipStream_t)stream));
 }
 
 }  // extern "C"

@@ -50,20 +50,18 @@ __device__ __forceinline__ void list_insert(float& ld, int& li, float v, int sv)
 }
 
 // Offer this chunk's candidates (cand = +inf where not admissible; s = time index) to one
-// list whose k-th entry (lane k1) is (thr, ithr).  The ballot pre-filters on d^2 <= thr;
-// the exact (d^2, index) test is made per survivor.
+// list whose k-th entry (lane k1) has d^2 = thr.  The ballot keeps candidates with
+// d^2 <= thr; a survivor that loses the (d^2, index) tie against the k-th entry is
+// inserted at lane k or beyond, outside the list, so no separate tie test is needed.
 __device__ __forceinline__ void offer_chunk(float cand, int s, float& ld, int& li, float& thr,
-                                            int& ithr, int k1) {
+                                            int k1) {
   uint64_t m = ballot(cand <= thr);
   while (m) {
     const int src = __ffsll((unsigned long long)m) - 1;
     const float v = readlane(cand, src);
     const int sv = readlane(s, src);
-    if (lex_less(v, sv, thr, ithr)) {
-      list_insert(ld, li, v, sv);
-      thr = readlane(ld, k1);
-      ithr = readlane(li, k1);
-    }
+    list_insert(ld, li, v, sv);
+    thr = readlane(ld, k1);
     m &= (~0ull << src) << 1;
     m &= ballot(cand <= thr);
   }
@@ -102,9 +100,11 @@ __device__ __forceinline__ double list_weight64(const float* x, int t, int nb, i
 
 // ---------------------------------------------------------------------------------------
 // Neighbour tables at each library's own E (one launch for every E).
-// grid.x = n_lib, block = 256 (4 waves); LDS: the library series.
+// grid.x = n_lib, block = 1024 (16 waves, one query each at a time); LDS: the series.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void knn_table_kernel(const float* __restrict__ ts, int64_t ld,
+constexpr int kKnnThreads = 1024;
+
+__global__ __launch_bounds__(kKnnThreads) void knn_table_kernel(const float* __restrict__ ts, int64_t ld,
                                                         int L, const int* __restrict__ lib_ids,
                                                         const int* __restrict__ lib_E, int tau,
                                                         int Tp, int k_max, int* __restrict__ nbr_idx,
@@ -147,7 +147,6 @@ __global__ __launch_bounds__(256) void knn_table_kernel(const float* __restrict_
     float ldist = INFINITY;
     int lidx = -1;
     float thr = INFINITY;
-    int ithr = -1;
     const int wb = window_base(t, lo, hi);
     // pass -1: the window around t; then every chunk in order, skipping the window
     for (int pass = -1, base = lo; base <= hi; base += (pass < 0 ? 0 : kWave), pass = 0) {
@@ -164,7 +163,7 @@ __global__ __launch_bounds__(256) void knn_table_kernel(const float* __restrict_
         }
       }
       float cand = (inr && s != t) ? acc : INFINITY;
-      offer_chunk(cand, s, ldist, lidx, thr, ithr, k - 1);
+      offer_chunk(cand, s, ldist, lidx, thr, k - 1);
     }
     double usum;
     double u = list_weight64(x, t, lidx, E, tau, k, usum);
@@ -226,13 +225,11 @@ __global__ __launch_bounds__(kSimplexThreads) void simplex_kernel(
     float ldist[kGroupE];
     int lidx[kGroupE];
     float thr[kGroupE];
-    int ithr[kGroupE];
 #pragma unroll
     for (int g = 0; g < kGroupE; ++g) {
       ldist[g] = INFINITY;
       lidx[g] = -1;
       thr[g] = INFINITY;
-      ithr[g] = -1;
     }
     // the window of candidates around t first (HALF mode: candidates are in the other
     // half, so the window clamps to its end), then every chunk in order
@@ -256,7 +253,7 @@ __global__ __launch_bounds__(kSimplexThreads) void simplex_kernel(
             float cand = adm ? acc : INFINITY;
 #pragma unroll
             for (int gg = 0; gg < kGroupE; ++gg)
-              if (gg == g) offer_chunk(cand, s, ldist[gg], lidx[gg], thr[gg], ithr[gg], E);
+              if (gg == g) offer_chunk(cand, s, ldist[gg], lidx[gg], thr[gg], E);
           }
         }
       }
@@ -354,7 +351,8 @@ extern "C" hipError_t ccm_launch_knn(const float* ts, int64_t ld, int L, const i
                                      hipStream_t stream) {
   if (n_lib == 0) return hipSuccess;
   size_t lds = (size_t)L * sizeof(float);
-  hipLaunchKernelGGL(ccm::knn_table_kernel, dim3(n_lib), dim3(256), lds, stream, ts, ld, L, lib_ids,
+  hipLaunchKernelGGL(ccm::knn_table_kernel, dim3(n_lib), dim3(ccm::kKnnThreads), lds, stream, ts, ld,
+                     L, lib_ids,
                      lib_E, tau, Tp, k_max, nbr_idx, nbr_w, nbr_d2);
   return hipGetLastError();
 }

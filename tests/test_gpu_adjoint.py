@@ -1,0 +1,90 @@
+"""GPU adjoint (ccm_crossmap_rho_backward through torch.autograd) against the FP64 oracle
+gradient, on the 2048-series coupled logistic network with 256 random pairs."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ccm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2011_11082_amd as m
+
+    m.load_library()
+    return m
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def test_adjoint_matches_fp64_oracle_logistic2048(ccm):
+    import torch
+
+    w = synth.make("logistic2048")
+    ts = w.panel
+    L, N = ts.shape
+    pairs = w.pairs
+    libs, lib_row = np.unique(pairs[:, 0], return_inverse=True)
+    lib_row = lib_row.astype(np.int32)
+    _say("adjoint: optE for", len(libs), "libraries")
+    Y = torch.as_tensor(ts).cuda()
+    optE, _ = ccm.simplex_optE(Y, libs.astype(np.int32), 1, 20, 1, 1)
+    lib_E = optE.cpu().numpy()
+    X = torch.as_tensor(np.ascontiguousarray(ts[:, libs].T)).cuda().requires_grad_(True)
+    Yg = Y.clone().requires_grad_(True)
+    _say("adjoint: forward + backward")
+    rho = ccm.crossmap_rho_autograd(X, Yg, optE)
+    sel = torch.zeros_like(rho)
+    sel[torch.as_tensor(lib_row).long().cuda(), torch.as_tensor(pairs[:, 1]).long().cuda()] = 1.0
+    loss = (rho * sel).sum()
+    loss.backward()
+    gX = X.grad.cpu().numpy().astype(np.float64)
+    gY = Yg.grad.cpu().numpy().astype(np.float64)
+    # oracle: same tables (bit-exact), FP64 gradient
+    idx_o, w_o, _ = O.knn(ts, libs, lib_E, 1, 0, int(lib_E.max()) + 1)
+    opairs = np.stack([lib_row, pairs[:, 1]], axis=1)
+    g_tgt, g_lib = O.crossmap_rho_grad(ts, libs, lib_E, idx_o, 1, opairs, np.ones(len(pairs)))
+    rt, rl = _rel(gY, g_tgt), _rel(gX, g_lib)
+    print(f"adjoint rel L2 error: targets {rt:.2e}, libraries {rl:.2e}")
+    assert rt < 1e-3 and rl < 1e-3
+    # invariants: rho is unchanged by y -> a y + b and by x -> a x + b
+    cols = np.unique(pairs[:, 1])
+    scale_t = np.abs(gY[:, cols]).sum(axis=0) + 1e-30
+    assert np.max(np.abs(gY[:, cols].sum(axis=0)) / scale_t) < 1e-4
+    scale_l = np.abs(gX).sum(axis=1) + 1e-30
+    assert np.max(np.abs(gX.sum(axis=1)) / scale_l) < 1e-4
+
+
+def test_adjoint_zero_and_nan_pairs(ccm):
+    import torch
+
+    rng = np.random.default_rng(3)
+    ts = rng.standard_normal((200, 6)).astype(np.float32)
+    ts[:, 5] = 1.0  # constant target: rho NaN, contributes no gradient
+    X = torch.as_tensor(np.ascontiguousarray(ts[:, :2].T)).cuda().requires_grad_(True)
+    Y = torch.as_tensor(ts).cuda().requires_grad_(True)
+    _say("adjoint: NaN pair")
+    rho = ccm.crossmap_rho_autograd(X, Y, [3, 2])
+    assert torch.isnan(rho[:, 5]).all()
+    g = torch.zeros_like(rho)
+    g[0, 5] = 1.0
+    g[1, 2] = 1.0
+    rho.backward(g)
+    assert torch.all(Y.grad[:, 5] == 0)
+    assert torch.isfinite(Y.grad).all() and torch.isfinite(X.grad).all()
+    assert Y.grad[:, 2].abs().sum() > 0 and X.grad[1].abs().sum() > 0 and X.grad[0].abs().sum() == 0
