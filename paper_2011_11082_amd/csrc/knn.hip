@@ -33,7 +33,31 @@
 namespace ccm {
 
 __device__ __forceinline__ bool lex_less(float a, int ia, float b, int ib) {
-  return a < b || (a == b && ia < ib);
+  return (a < b) | ((a == b) & (ia < ib));
+}
+
+// The series sits in LDS after kPad zeros, so x[-kPad .. -1] reads 0 and lag reads at
+// tau = 1 need no clamp.
+constexpr int kPad = 32;
+
+// Lag values x[sc - e tau], e = 0..NL-1, of the candidate at sc; all NL reads are issued
+// before the arithmetic.  With tau = 1 they are one base address plus immediate offsets.
+template <int NL, bool TAU1>
+__device__ __forceinline__ void lag_values(const float* x, int sc, int tau, float (&xs)[NL]) {
+  if constexpr (TAU1) {
+    // one unsigned byte address (never negative: x is preceded by kPad >= NL zeros) plus
+    // immediate offsets
+    const char* lds0 = (const char*)(x - kPad);
+    const uint32_t a = (uint32_t)(sc + kPad - (NL - 1)) * 4u;
+#pragma unroll
+    for (int e = 0; e < NL; ++e) xs[e] = *(const float*)(lds0 + a + 4u * (NL - 1 - e));
+  } else {
+#pragma unroll
+    for (int e = 0; e < NL; ++e) {
+      const int xi = sc - e * tau;
+      xs[e] = x[xi > 0 ? xi : 0];
+    }
+  }
 }
 
 // Insert candidate (v, sv) into the wave-distributed list (ld, li), ascending in
@@ -104,22 +128,61 @@ __device__ __forceinline__ double list_weight64(const float* x, int t, int nb, i
 // ---------------------------------------------------------------------------------------
 constexpr int kKnnThreads = 1024;
 
+// The scan of one query at a compile-time E: every candidate chunk's lag reads are issued
+// together, then the canonical d^2 is formed in lag order.
+template <int E, bool TAU1>
+__device__ __forceinline__ void knn_query(const float* x, int t, int lo, int hi, int tau,
+                                          float& ldist, int& lidx) {
+  const int lane = lane_id();
+  float xq[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+    xq[e] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x[t - e * tau])));
+  ldist = INFINITY;
+  lidx = -1;
+  float thr = INFINITY;
+  const int wb = window_base(t, lo, hi);
+  // pass -1: the window around t; then every chunk in order, skipping the window
+  for (int pass = -1, base = lo; base <= hi; base += (pass < 0 ? 0 : kWave), pass = 0) {
+    const int b = pass < 0 ? wb : base;
+    const int s = b + lane;
+    const bool inr = s <= hi && (pass < 0 || s < wb || s >= wb + kWave);
+    const int sc = s <= hi ? s : hi;
+    float xs[E];
+    lag_values<E, TAU1>(x, sc, tau, xs);
+    float acc = 0.0f;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const float df = xq[e] - xs[e];
+      acc = acc + df * df;
+    }
+    const float cand = (inr && s != t) ? acc : INFINITY;
+    offer_chunk(cand, s, ldist, lidx, thr, E);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Neighbour tables at each library's own E (one launch for every E).
+// grid.x = n_lib, block = 1024 (16 waves, one query each at a time); LDS: the series.
+// ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kKnnThreads) void knn_table_kernel(const float* __restrict__ ts, int64_t ld,
                                                         int L, const int* __restrict__ lib_ids,
                                                         const int* __restrict__ lib_E, int tau,
                                                         int Tp, int k_max, int* __restrict__ nbr_idx,
                                                         float* __restrict__ nbr_w,
                                                         float* __restrict__ nbr_d2) {
-  extern __shared__ float x[];
+  extern __shared__ float xbuf[];
+  float* x = xbuf + kPad;
   const int lib = blockIdx.x;
   const int sid = lib_ids[lib];
-  for (int t = threadIdx.x; t < L; t += blockDim.x) x[t] = ts[(int64_t)t * ld + sid];
+  for (int t = threadIdx.x; t < L + kPad; t += blockDim.x)
+    xbuf[t] = t < kPad ? 0.0f : ts[(int64_t)(t - kPad) * ld + sid];
   __syncthreads();
 
   const int lane = lane_id();
-  const int wave = threadIdx.x / kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int nw = blockDim.x / kWave;
-  const int E = lib_E[lib];
+  const int E = __builtin_amdgcn_readfirstlane(lib_E[lib]);
   const int k = E + 1;
   const int lo = (E - 1) * tau;           // first point
   const int hi = L - 1 - Tp;              // last point with a future
@@ -138,32 +201,23 @@ __global__ __launch_bounds__(kKnnThreads) void knn_table_kernel(const float* __r
       }
       continue;
     }
-    float xq[kEMax];
-#pragma unroll
-    for (int e = 0; e < kEMax; ++e)
-      xq[e] = __int_as_float(
-          __builtin_amdgcn_readfirstlane(__float_as_int((e < E) ? x[t - e * tau] : 0.0f)));
-
-    float ldist = INFINITY;
-    int lidx = -1;
-    float thr = INFINITY;
-    const int wb = window_base(t, lo, hi);
-    // pass -1: the window around t; then every chunk in order, skipping the window
-    for (int pass = -1, base = lo; base <= hi; base += (pass < 0 ? 0 : kWave), pass = 0) {
-      const int b = pass < 0 ? wb : base;
-      const int s = b + lane;
-      const bool inr = s <= hi && (pass < 0 || s < wb || s >= wb + kWave);
-      const int sc = s <= hi ? s : hi;
-      float acc = 0.0f;
-#pragma unroll
-      for (int e = 0; e < kEMax; ++e) {
-        if (e < E) {
-          float df = xq[e] - x[sc - e * tau];
-          acc = acc + df * df;
-        }
-      }
-      float cand = (inr && s != t) ? acc : INFINITY;
-      offer_chunk(cand, s, ldist, lidx, thr, k - 1);
+    float ldist;
+    int lidx;
+    switch (E) {
+#define CCM_E(EE)                                            \
+  case EE:                                                   \
+    if (tau == 1)                                            \
+      knn_query<EE, true>(x, t, lo, hi, tau, ldist, lidx);   \
+    else                                                     \
+      knn_query<EE, false>(x, t, lo, hi, tau, ldist, lidx);  \
+    break;
+      CCM_E(1) CCM_E(2) CCM_E(3) CCM_E(4) CCM_E(5) CCM_E(6) CCM_E(7) CCM_E(8) CCM_E(9) CCM_E(10)
+      CCM_E(11) CCM_E(12) CCM_E(13) CCM_E(14) CCM_E(15) CCM_E(16) CCM_E(17) CCM_E(18) CCM_E(19)
+      CCM_E(20)
+#undef CCM_E
+      default:
+        ldist = INFINITY;
+        lidx = -1;
     }
     double usum;
     double u = list_weight64(x, t, lidx, E, tau, k, usum);
@@ -177,35 +231,24 @@ __global__ __launch_bounds__(kKnnThreads) void knn_table_kernel(const float* __r
 }
 
 // ---------------------------------------------------------------------------------------
-// Simplex projection skill for E = E_lo..E_hi (at most kGroupE values), one workgroup per
-// (series, E group).  The squared distance is accumulated over lags 0..E_hi-1 once; each
-// E of the group keeps its own list.  LOO: Q_E = C_E = [(E-1)tau, L-1-Tp], query excluded.
-// HALF: C_E = [(E-1)tau, h-1-Tp], Q_E = [h+(E-1)tau, L-1-Tp], h = L/2, no exclusion.
-// Writes the FP64 skill of each E to rho64[series][E-1].
+// Simplex projection skill, one workgroup per (series, E group).  Groups are fixed at
+// E = 1..10, 11..16, 17..20 (about equal work: lags grow with E, and so do the lists) and
+// clipped to [E_min, E_max].  The squared distance is accumulated over lags 0..EHI-1 once;
+// each E of the group keeps its own list.  LOO: Q_E = C_E = [(E-1)tau, L-1-Tp], query
+// excluded.  HALF: C_E = [(E-1)tau, h-1-Tp], Q_E = [h+(E-1)tau, L-1-Tp], h = L/2, no
+// exclusion.  Writes the FP64 skill of each E to rho64[series][E-1].
 // ---------------------------------------------------------------------------------------
 constexpr int kSimplexThreads = 512;
 constexpr int kGroupE = 10;
 
-struct EGroups {
-  int lo[3];
-  int hi[3];
-};
-
-__global__ __launch_bounds__(kSimplexThreads) void simplex_kernel(
-    const float* __restrict__ ts, int64_t ld, int L, const int* __restrict__ ids, EGroups groups,
-    int tau, int Tp, int mode, double* __restrict__ rho64) {
-  extern __shared__ float x[];
-  __shared__ double wsum[kSimplexThreads / kWave][kGroupE][5];
-  const int sid = ids[blockIdx.x];
-  const int E_lo = groups.lo[blockIdx.y];
-  const int E_hi = groups.hi[blockIdx.y];
-  for (int t = threadIdx.x; t < L; t += blockDim.x) x[t] = ts[(int64_t)t * ld + sid];
-  __syncthreads();
-
+template <int ELO, int EHI, bool TAU1>
+__device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, int E_max, int tau,
+                                              int Tp, bool half, int wave, int nw,
+                                              double (&wsum)[kSimplexThreads / kWave][kGroupE][5]) {
+  constexpr int NG = EHI - ELO + 1;
   const int lane = lane_id();
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int nw = blockDim.x / kWave;
-  const bool half = mode == 1;
+  const int E_lo = ELO > E_min ? ELO : E_min;
+  const int E_hi = EHI < E_max ? EHI : E_max;
   const int h = L / 2;
   const int qbase = half ? h : 0;
   const int chi = half ? h - 1 - Tp : L - 1 - Tp;     // last candidate
@@ -213,20 +256,20 @@ __global__ __launch_bounds__(kSimplexThreads) void simplex_kernel(
   const int qlo = qbase + (E_lo - 1) * tau;
   const int qhi = L - 1 - Tp;
 
-  // lane g holds the five FP64 moment sums of E = E_lo + g
+  // lane g holds the five FP64 moment sums of E = ELO + g
   double m_o = 0.0, m_oo = 0.0, m_p = 0.0, m_pp = 0.0, m_op = 0.0;
 
   for (int t = qlo + wave; t <= qhi; t += nw) {
-    float xq[kEMax];
+    float xq[EHI];
 #pragma unroll
-    for (int e = 0; e < kEMax; ++e)
+    for (int e = 0; e < EHI; ++e)
       xq[e] = __int_as_float(__builtin_amdgcn_readfirstlane(
-          __float_as_int((e < E_hi && t - e * tau >= 0) ? x[t - e * tau] : 0.0f)));
-    float ldist[kGroupE];
-    int lidx[kGroupE];
-    float thr[kGroupE];
+          __float_as_int(t - e * tau >= 0 ? x[t - e * tau] : 0.0f)));
+    float ldist[NG];
+    int lidx[NG];
+    float thr[NG];
 #pragma unroll
-    for (int g = 0; g < kGroupE; ++g) {
+    for (int g = 0; g < NG; ++g) {
       ldist[g] = INFINITY;
       lidx[g] = -1;
       thr[g] = INFINITY;
@@ -239,30 +282,32 @@ __global__ __launch_bounds__(kSimplexThreads) void simplex_kernel(
       const int s = b + lane;
       const bool inr = s <= chi && (pass < 0 || s < wb || s >= wb + kWave);
       const int sc = s <= chi ? s : chi;
+      float xs[EHI];
+      lag_values<EHI, TAU1>(x, sc, tau, xs);
       float acc = 0.0f;
 #pragma unroll
-      for (int e = 0; e < kEMax; ++e) {
-        if (e < E_hi) {
-          const int xi = sc - e * tau;
-          float df = xq[e] - x[xi > 0 ? xi : 0];
-          acc = acc + df * df;
+      for (int e = 0; e < EHI; ++e) {
+        const float df = xq[e] - xs[e];
+        acc = acc + df * df;
+        constexpr int dummy = 0;
+        (void)dummy;
+        if (e + 1 >= ELO) {
           const int E = e + 1;
-          const int g = E - E_lo;
-          if (g >= 0 && t >= qbase + (E - 1) * tau) {
+          if (E >= E_lo && E <= E_hi && t >= qbase + (E - 1) * tau) {
             const bool adm = inr && sc >= (E - 1) * tau && (half || s != t);
-            float cand = adm ? acc : INFINITY;
-#pragma unroll
-            for (int gg = 0; gg < kGroupE; ++gg)
-              if (gg == g) offer_chunk(cand, s, ldist[gg], lidx[gg], thr[gg], E);
+            const float cand = adm ? acc : INFINITY;
+            offer_chunk(cand, s, ldist[(e + 1 - ELO) >= 0 ? (e + 1 - ELO) : 0],
+                        lidx[(e + 1 - ELO) >= 0 ? (e + 1 - ELO) : 0],
+                        thr[(e + 1 - ELO) >= 0 ? (e + 1 - ELO) : 0], E);
           }
         }
       }
     }
     const float obs = x[t + Tp];
 #pragma unroll
-    for (int g = 0; g < kGroupE; ++g) {
-      const int E = E_lo + g;
-      if (E <= E_hi && t >= qbase + (E - 1) * tau) {
+    for (int g = 0; g < NG; ++g) {
+      const int E = ELO + g;
+      if (E >= E_lo && E <= E_hi && t >= qbase + (E - 1) * tau) {
         double usum;
         double u = list_weight64(x, t, lidx[g], E, tau, E + 1, usum);
         double f = (lane <= E && lidx[g] >= 0) ? (double)x[lidx[g] + Tp] : 0.0;
@@ -285,15 +330,48 @@ __global__ __launch_bounds__(kSimplexThreads) void simplex_kernel(
     wsum[wave][lane][3] = m_pp;
     wsum[wave][lane][4] = m_op;
   }
+}
+
+__global__ __launch_bounds__(kSimplexThreads) void simplex_kernel(
+    const float* __restrict__ ts, int64_t ld, int L, const int* __restrict__ ids, int E_min,
+    int E_max, int tau, int Tp, int mode, double* __restrict__ rho64) {
+  extern __shared__ float xbuf[];
+  float* x = xbuf + kPad;
+  __shared__ double wsum[kSimplexThreads / kWave][kGroupE][5];
+  const int grp = blockIdx.y;
+  const int ELO = grp == 0 ? 1 : (grp == 1 ? 11 : 17);
+  const int EHI = grp == 0 ? 10 : (grp == 1 ? 16 : 20);
+  const int E_lo = ELO > E_min ? ELO : E_min;
+  const int E_hi = EHI < E_max ? EHI : E_max;
+  if (E_lo > E_hi) return;  // whole workgroup: group outside [E_min, E_max]
+  const int sid = ids[blockIdx.x];
+  for (int t = threadIdx.x; t < L + kPad; t += blockDim.x)
+    xbuf[t] = t < kPad ? 0.0f : ts[(int64_t)(t - kPad) * ld + sid];
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int nw = blockDim.x / kWave;
+  const bool half = mode == 1;
+  if (grp == 0) {
+    if (tau == 1) simplex_group<1, 10, true>(x, L, E_min, E_max, tau, Tp, half, wave, nw, wsum);
+    else simplex_group<1, 10, false>(x, L, E_min, E_max, tau, Tp, half, wave, nw, wsum);
+  } else if (grp == 1) {
+    if (tau == 1) simplex_group<11, 16, true>(x, L, E_min, E_max, tau, Tp, half, wave, nw, wsum);
+    else simplex_group<11, 16, false>(x, L, E_min, E_max, tau, Tp, half, wave, nw, wsum);
+  } else {
+    if (tau == 1) simplex_group<17, 20, true>(x, L, E_min, E_max, tau, Tp, half, wave, nw, wsum);
+    else simplex_group<17, 20, false>(x, L, E_min, E_max, tau, Tp, half, wave, nw, wsum);
+  }
   __syncthreads();
   if (threadIdx.x < kGroupE) {
     const int g = threadIdx.x;
-    const int E = E_lo + g;
-    if (E <= E_hi) {
+    const int E = ELO + g;
+    if (E >= E_lo && E <= E_hi) {
       double sm[5] = {0, 0, 0, 0, 0};
       for (int w = 0; w < nw; ++w)
         for (int c = 0; c < 5; ++c) sm[c] += wsum[w][g][c];
+      const int qbase = half ? L / 2 : 0;
       const int qfirst = qbase + (E - 1) * tau;
+      const int qhi = L - 1 - Tp;
       const double n = (double)(qhi - qfirst + 1);
       rho64[(size_t)blockIdx.x * kEMax + (E - 1)] =
           n > 0 ? pearson_from_moments(n, sm[0], sm[1], sm[2], sm[3], sm[4]) : __builtin_nan("");
@@ -350,7 +428,7 @@ extern "C" hipError_t ccm_launch_knn(const float* ts, int64_t ld, int L, const i
                                      int* nbr_idx, float* nbr_w, float* nbr_d2,
                                      hipStream_t stream) {
   if (n_lib == 0) return hipSuccess;
-  size_t lds = (size_t)L * sizeof(float);
+  size_t lds = (size_t)(L + ccm::kPad) * sizeof(float);
   hipLaunchKernelGGL(ccm::knn_table_kernel, dim3(n_lib), dim3(ccm::kKnnThreads), lds, stream, ts, ld,
                      L, lib_ids,
                      lib_E, tau, Tp, k_max, nbr_idx, nbr_w, nbr_d2);
@@ -362,23 +440,9 @@ extern "C" hipError_t ccm_launch_simplex(const float* ts, int64_t ld, int L, con
                                          int* optE, float* rho_E, double* rho64,
                                          hipStream_t stream) {
   if (n == 0) return hipSuccess;
-  // E groups of about equal work (lags grow with E, and so do list sizes)
-  static const int kLo[3] = {1, 11, 17};
-  static const int kHi[3] = {10, 16, 20};
-  ccm::EGroups grp;
-  int ng = 0;
-  for (int g = 0; g < 3; ++g) {
-    int lo = kLo[g] > E_min ? kLo[g] : E_min;
-    int hi = kHi[g] < E_max ? kHi[g] : E_max;
-    if (lo <= hi) {
-      grp.lo[ng] = lo;
-      grp.hi[ng] = hi;
-      ++ng;
-    }
-  }
-  size_t lds = (size_t)L * sizeof(float);
-  hipLaunchKernelGGL(ccm::simplex_kernel, dim3(n, ng), dim3(ccm::kSimplexThreads), lds, stream, ts,
-                     ld, L, ids, grp, tau, Tp, mode, rho64);
+  size_t lds = (size_t)(L + ccm::kPad) * sizeof(float);
+  hipLaunchKernelGGL(ccm::simplex_kernel, dim3(n, 3), dim3(ccm::kSimplexThreads), lds, stream, ts,
+                     ld, L, ids, E_min, E_max, tau, Tp, mode, rho64);
   hipLaunchKernelGGL(ccm::simplex_finalize_kernel, dim3((n + 255) / 256), dim3(256), 0, stream,
                      rho64, n, E_min, E_max, optE, rho_E);
   return hipGetLastError();
