@@ -137,6 +137,20 @@ __global__ __launch_bounds__(256) void prep_tables_kernel(
 // The gather.  grid = (target tiles, library splits), block = 1024 threads.
 // LDS: tile [L][16] floats, then column sums sy[E][16], syy[E][16] (FP64, E = 1..20).
 // ---------------------------------------------------------------------------------------
+// acc.xyzw += bcast_M(w) * y.xyzw, the weight broadcast inside the quad folded into the
+// FMAs as a DPP operand.  The leading s_nop covers the DPP read-after-VALU-write hazard.
+template <int M>
+__device__ __forceinline__ void fma4_bcast(float4& acc, float w, const float4& y) {
+  asm volatile(
+      "s_nop 1\n\t"
+      "v_fmac_f32_dpp %0, %4, %5 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %1, %4, %6 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %2, %4, %7 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %3, %4, %9 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1"
+      : "+v"(acc.x), "+v"(acc.y), "+v"(acc.z), "+v"(acc.w)
+      : "v"(w), "v"(y.x), "v"(y.y), "v"(y.z), "n"(M), "v"(y.w));
+}
+
 // Steps J .. J+3 of one table row: the four 128-bit LDS reads are issued before any of
 // their products, so several reads are in flight per wave.
 template <int J, int K>
@@ -156,20 +170,10 @@ __device__ __forceinline__ void gather_quad(const char* tile, const uint32_t (&o
       y[q] = *(const float4*)(tile + o + laneoff);
     }
   }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    if (J + q < K) {
-      float w;
-      if (q == 0) w = quad_bcast<0>(wgt[S]);
-      if (q == 1) w = quad_bcast<1>(wgt[S]);
-      if (q == 2) w = quad_bcast<2>(wgt[S]);
-      if (q == 3) w = quad_bcast<3>(wgt[S]);
-      acc.x = fmaf(w, y[q].x, acc.x);
-      acc.y = fmaf(w, y[q].y, acc.y);
-      acc.z = fmaf(w, y[q].z, acc.z);
-      acc.w = fmaf(w, y[q].w, acc.w);
-    }
-  }
+  if (J + 0 < K) fma4_bcast<0>(acc, wgt[S], y[0]);
+  if (J + 1 < K) fma4_bcast<1>(acc, wgt[S], y[1]);
+  if (J + 2 < K) fma4_bcast<2>(acc, wgt[S], y[2]);
+  if (J + 3 < K) fma4_bcast<3>(acc, wgt[S], y[3]);
 }
 
 template <int K, int J = 0>
@@ -204,30 +208,36 @@ __device__ __forceinline__ void gather_library(const char* smem, const uint32_t*
                                                Moments& m) {
   constexpr int KS = (K + 3) / 4;
   const int lane = lane_id();
+  const size_t bstride = (size_t)KSM * kWave;   // entries per block
+  // block pointers are uniform (scalar base + lane offset + immediate slot offset); the
+  // workspace holds one spare block after the last library, so the prefetch of block b + 1
+  // is always in bounds
+  const uint32_t* bo = po + (size_t)b0 * bstride;
+  const float* bw = pq + (size_t)b0 * bstride;
   uint32_t off[KS];
   float wgt[KS];
 #pragma unroll
   for (int s4 = 0; s4 < KS; ++s4) {
-    const size_t p = ((size_t)b0 * KSM + s4) * kWave + lane;
-    off[s4] = po[p];
-    wgt[s4] = pq[p];
+    off[s4] = bo[s4 * kWave + lane];
+    wgt[s4] = bw[s4 * kWave + lane];
   }
   int since = 0;
+  const char* yrow = smem + laneoff;
   for (int b = b0; b < nblk; ++b) {
+    bo += bstride;
+    bw += bstride;
     uint32_t offn[KS];
     float wgtn[KS];
-    const int bn = b + 1 < nblk ? b + 1 : b;
 #pragma unroll
     for (int s4 = 0; s4 < KS; ++s4) {
-      const size_t p = ((size_t)bn * KSM + s4) * kWave + lane;
-      offn[s4] = po[p];
-      wgtn[s4] = pq[p];
+      offn[s4] = bo[s4 * kWave + lane];
+      wgtn[s4] = bw[s4 * kWave + lane];
     }
     float4 acc = {0, 0, 0, 0};
     gather_row<K>(smem, off, wgt, laneoff, acc);
     int t = b * 16 + G;
     t = t < L ? t : L - 1;
-    const float4 yo = *(const float4*)(smem + (size_t)t * kRowBytes + laneoff);
+    const float4 yo = *(const float4*)(yrow + (uint32_t)t * kRowBytes);
     m.sp.x += acc.x; m.sp.y += acc.y; m.sp.z += acc.z; m.sp.w += acc.w;
     m.spp.x = fmaf(acc.x, acc.x, m.spp.x); m.spp.y = fmaf(acc.y, acc.y, m.spp.y);
     m.spp.z = fmaf(acc.z, acc.z, m.spp.z); m.spp.w = fmaf(acc.w, acc.w, m.spp.w);
