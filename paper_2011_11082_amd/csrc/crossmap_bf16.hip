@@ -130,6 +130,9 @@ __global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
   uint16_t* Bs = (uint16_t*)smem;
   uint16_t* As = (uint16_t*)(smem + 2 * kBTN * kStage * 2);
   double* momb = (double*)(smem + 2 * kBTN * kStage * 2 + 4 * kHalf * kStage * 2);
+  // the current chunk's sorted entries and stage offsets of both libraries
+  uint32_t* Es = (uint32_t*)(momb + 4 * 5 * 4 * kWave);
+  int* Ss = (int*)(Es + 2 * kBRows * kKMax);
   const int lane = lane_id();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int half = wave & 1;     // rows 64*half .. 64*half+63 of each 128-row chunk
@@ -167,12 +170,22 @@ __global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
     const bool mine = c < nchunk;
-    const uint32_t* eo = ent + ((size_t)i * nchunk_max + c) * (kBRows * kKMax);
-    const int* so = stage_off + ((size_t)i * nchunk_max + c) * (nst + 1);
+    // stage this chunk's entries and offsets in LDS (the two waves of a library split the copy)
+    uint32_t* eo = Es + (size_t)(wave >> 1) * kBRows * kKMax;
+    int* so = Ss + (size_t)(wave >> 1) * (kMaxStages + 1);
+    __syncthreads();  // previous chunk is done with Es / Ss
+    if (mine) {
+      const uint32_t* eg = ent + ((size_t)i * nchunk_max + c) * (kBRows * kKMax);
+      const int* sg = stage_off + ((size_t)i * nchunk_max + c) * (nst + 1);
+      const int ne = sg[nst];
+      for (int q = half * kWave + lane; q <= nst; q += 2 * kWave) so[q] = sg[q];
+      for (int q = half * kWave + lane; q < ne; q += 2 * kWave) eo[q] = eg[q];
+    }
     uint4 breg[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       breg[q] = brow_ok ? *(const uint4*)(ysrc + q * 8) : uint4{0, 0, 0, 0};
+    __syncthreads();  // staged entries visible to both waves of each library
     for (int st = 0; st < nst; ++st) {
       const int buf = st & 1;
       // scatter this wave's nonzeros of the stage (rows of its half only)
@@ -290,7 +303,8 @@ extern "C" hipError_t ccm_launch_order(const int* lib_k, int n_lib, int* order, 
 
 extern "C" size_t ccm_bf16_lds_bytes() {
   return 2 * (size_t)ccm::kBTN * ccm::kStage * 2 + 4 * (size_t)ccm::kHalf * ccm::kStage * 2 +
-         4 * 5 * 4 * (size_t)ccm::kWave * sizeof(double);
+         4 * 5 * 4 * (size_t)ccm::kWave * sizeof(double) +
+         2 * (size_t)ccm::kBRows * ccm::kKMax * 4 + 2 * (size_t)(ccm::kMaxStages + 1) * 4;
 }
 
 extern "C" hipError_t ccm_launch_crossmap_bf16(const float* ts, int64_t ld, int L, int tau, int tgt0,
