@@ -32,8 +32,52 @@
 
 namespace ccm {
 
-__device__ __forceinline__ bool lex_less(float a, int ia, float b, int ib) {
-  return (a < b) | ((a == b) & (ia < ib));
+// A list entry is the 64-bit key (bits of d^2) << 32 | time index: d^2 >= 0, so its IEEE
+// bits order like the value, and comparing keys as unsigned integers is exactly the
+// (d^2, time index) order.  Empty slots and inadmissible candidates hold ~0.
+__device__ __forceinline__ uint64_t nkey(float d2, int s) {
+  return ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)s;
+}
+__device__ __forceinline__ float key_d2(uint64_t k) { return __uint_as_float((uint32_t)(k >> 32)); }
+__device__ __forceinline__ int key_idx(uint64_t k) { return (int)(uint32_t)k; }
+
+__device__ __forceinline__ uint64_t readlane(uint64_t v, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Insert key kv into the wave-distributed ascending list (lane j = j-th smallest).  A key
+// larger than the k-th entry lands at lane k or beyond, outside the list.
+__device__ __forceinline__ void list_insert(uint64_t& key, uint64_t kv) {
+  const uint32_t plo = (uint32_t)wave_shr1((int)(uint32_t)key, 0);
+  const uint32_t phi = (uint32_t)wave_shr1((int)(uint32_t)(key >> 32), 0);
+  const uint64_t prev = ((uint64_t)phi << 32) | plo;  // lane 0: 0, below every key
+  const bool gt = key > kv;
+  const bool gtp = prev > kv;
+  const uint64_t nk = gtp ? prev : kv;
+  key = gt ? nk : key;
+}
+
+// Offer this chunk's candidate keys (~0 where not admissible) to one list whose k-th entry
+// sits in lane k1; `thr` is that entry's key.  Survivors are inserted one at a time.
+__device__ __forceinline__ void offer_chunk(uint64_t cand, uint64_t& key, uint64_t& thr, int k1) {
+  uint64_t m = ballot(cand < thr);
+  while (m) {
+    const int src = __ffsll((unsigned long long)m) - 1;
+    list_insert(key, readlane(cand, src));
+    thr = readlane(key, k1);
+    m &= (~0ull << src) << 1;
+    m &= ballot(cand < thr);
+  }
+}
+
+// First chunk base of the scan: the 64 points centred on the query, inside [clo, chi].
+__device__ __forceinline__ int window_base(int t, int clo, int chi) {
+  int b = t - 32;
+  if (b > chi - (kWave - 1)) b = chi - (kWave - 1);
+  if (b < clo) b = clo;
+  return b;
 }
 
 // The series sits in LDS after kPad zeros, so x[-kPad .. -1] reads 0 and lag reads at
@@ -58,45 +102,6 @@ __device__ __forceinline__ void lag_values(const float* x, int sc, int tau, floa
       xs[e] = x[xi > 0 ? xi : 0];
     }
   }
-}
-
-// Insert candidate (v, sv) into the wave-distributed list (ld, li), ascending in
-// (d^2, time index).
-__device__ __forceinline__ void list_insert(float& ld, int& li, float v, int sv) {
-  float pd = wave_shr1(ld, -INFINITY);
-  int pi = wave_shr1(li, -1);
-  bool gt = lex_less(v, sv, ld, li);
-  bool gtp = lex_less(v, sv, pd, pi);
-  float nd = gtp ? pd : v;
-  int ni = gtp ? pi : sv;
-  ld = gt ? nd : ld;
-  li = gt ? ni : li;
-}
-
-// Offer this chunk's candidates (cand = +inf where not admissible; s = time index) to one
-// list whose k-th entry (lane k1) has d^2 = thr.  The ballot keeps candidates with
-// d^2 <= thr; a survivor that loses the (d^2, index) tie against the k-th entry is
-// inserted at lane k or beyond, outside the list, so no separate tie test is needed.
-__device__ __forceinline__ void offer_chunk(float cand, int s, float& ld, int& li, float& thr,
-                                            int k1) {
-  uint64_t m = ballot(cand <= thr);
-  while (m) {
-    const int src = __ffsll((unsigned long long)m) - 1;
-    const float v = readlane(cand, src);
-    const int sv = readlane(s, src);
-    list_insert(ld, li, v, sv);
-    thr = readlane(ld, k1);
-    m &= (~0ull << src) << 1;
-    m &= ballot(cand <= thr);
-  }
-}
-
-// First chunk base of the scan: the 64 points centred on the query, inside [clo, chi].
-__device__ __forceinline__ int window_base(int t, int clo, int chi) {
-  int b = t - 32;
-  if (b > chi - (kWave - 1)) b = chi - (kWave - 1);
-  if (b < clo) b = clo;
-  return b;
 }
 
 // Simplex weights of a finished list (lanes 0..k-1 hold neighbour n_j of query t).  The
@@ -138,9 +143,8 @@ __device__ __forceinline__ void knn_query(const float* x, int t, int lo, int hi,
 #pragma unroll
   for (int e = 0; e < E; ++e)
     xq[e] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x[t - e * tau])));
-  ldist = INFINITY;
-  lidx = -1;
-  float thr = INFINITY;
+  uint64_t key = ~0ull;
+  uint64_t thr = ~0ull;
   const int wb = window_base(t, lo, hi);
   // pass -1: the window around t; then every chunk in order, skipping the window
   for (int pass = -1, base = lo; base <= hi; base += (pass < 0 ? 0 : kWave), pass = 0) {
@@ -156,9 +160,11 @@ __device__ __forceinline__ void knn_query(const float* x, int t, int lo, int hi,
       const float df = xq[e] - xs[e];
       acc = acc + df * df;
     }
-    const float cand = (inr && s != t) ? acc : INFINITY;
-    offer_chunk(cand, s, ldist, lidx, thr, E);
+    const uint64_t cand = (inr && s != t) ? nkey(acc, s) : ~0ull;
+    offer_chunk(cand, key, thr, E);
   }
+  ldist = key_d2(key);
+  lidx = key_idx(key);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -265,15 +271,10 @@ __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, 
     for (int e = 0; e < EHI; ++e)
       xq[e] = __int_as_float(__builtin_amdgcn_readfirstlane(
           __float_as_int(t - e * tau >= 0 ? x[t - e * tau] : 0.0f)));
-    float ldist[NG];
-    int lidx[NG];
-    float thr[NG];
+    uint64_t key[NG];
+    uint64_t thr[NG];
 #pragma unroll
-    for (int g = 0; g < NG; ++g) {
-      ldist[g] = INFINITY;
-      lidx[g] = -1;
-      thr[g] = INFINITY;
-    }
+    for (int g = 0; g < NG; ++g) key[g] = thr[g] = ~0ull;
     // the window of candidates around t first (HALF mode: candidates are in the other
     // half, so the window clamps to its end), then every chunk in order
     const int wb = window_base(t, clo, chi);
@@ -289,16 +290,13 @@ __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, 
       for (int e = 0; e < EHI; ++e) {
         const float df = xq[e] - xs[e];
         acc = acc + df * df;
-        constexpr int dummy = 0;
-        (void)dummy;
         if (e + 1 >= ELO) {
           const int E = e + 1;
           if (E >= E_lo && E <= E_hi && t >= qbase + (E - 1) * tau) {
             const bool adm = inr && sc >= (E - 1) * tau && (half || s != t);
-            const float cand = adm ? acc : INFINITY;
-            offer_chunk(cand, s, ldist[(e + 1 - ELO) >= 0 ? (e + 1 - ELO) : 0],
-                        lidx[(e + 1 - ELO) >= 0 ? (e + 1 - ELO) : 0],
-                        thr[(e + 1 - ELO) >= 0 ? (e + 1 - ELO) : 0], E);
+            const uint64_t cand = adm ? nkey(acc, s) : ~0ull;
+            const int g = (e + 1 - ELO) >= 0 ? (e + 1 - ELO) : 0;
+            offer_chunk(cand, key[g], thr[g], E);
           }
         }
       }
@@ -308,9 +306,10 @@ __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, 
     for (int g = 0; g < NG; ++g) {
       const int E = ELO + g;
       if (E >= E_lo && E <= E_hi && t >= qbase + (E - 1) * tau) {
+        const int li = lane <= E ? key_idx(key[g]) : -1;
         double usum;
-        double u = list_weight64(x, t, lidx[g], E, tau, E + 1, usum);
-        double f = (lane <= E && lidx[g] >= 0) ? (double)x[lidx[g] + Tp] : 0.0;
+        double u = list_weight64(x, t, li, E, tau, E + 1, usum);
+        double f = (lane <= E && li >= 0) ? (double)x[li + Tp] : 0.0;
         double pred = wave_sum(u * f) / usum;
         if (lane == g) {
           double o = obs, p = pred;
