@@ -88,3 +88,20 @@ def test_argument_errors_return_status_before_device_work():
     # L beyond the FP32 tile
     assert lib.ccm_crossmap_rho(fake, 64, 4000, fake, fake, fake, 4, 21, 1, 0, 64, 0, fake,
                                 _null(), _null(), 0, _null()) == ccm.CCM_ENOTSUP
+
+
+def test_backward_argument_errors():
+    lib = ccm.load_library()
+    fake = ctypes.c_void_p(0x1000)
+    # both gradients NULL
+    assert lib.ccm_crossmap_rho_backward(fake, 8, 100, fake, fake, fake, fake, 2, 4, 1, fake, fake,
+                                         fake, 3, _null(), _null(), fake, 1 << 20,
+                                         _null()) == ccm.CCM_EINVAL
+    # workspace too small
+    assert lib.ccm_crossmap_rho_backward(fake, 8, 100, fake, fake, fake, fake, 2, 4, 1, fake, fake,
+                                         fake, 3, fake, fake, fake, 16, _null()) == ccm.CCM_EWORKSPACE
+    # zero pairs: nothing to do
+    assert lib.ccm_crossmap_rho_backward(fake, 8, 100, fake, fake, fake, fake, 2, 4, 1, fake, fake,
+                                         fake, 0, fake, fake, _null(), 0, _null()) == ccm.CCM_OK
+    n = ccm.workspace_size(ccm.OP_CROSSMAP_BACKWARD, 1000, 2048, 256, 21)
+    assert n >= 256 * 1000 * 21 * 4
