@@ -210,17 +210,22 @@ __device__ __forceinline__ void gather_library(const char* smem, const uint32_t*
   const int lane = lane_id();
   const size_t bstride = (size_t)KSM * kWave;   // entries per block
   // block pointers are uniform (scalar base + lane offset + immediate slot offset); the
-  // workspace holds one spare block after the last library, so the prefetch of block b + 1
+  // workspace holds two spare blocks after the last library, so the prefetch of block b + 2
   // is always in bounds
   const uint32_t* bo = po + (size_t)b0 * bstride;
   const float* bw = pq + (size_t)b0 * bstride;
-  uint32_t off[KS];
-  float wgt[KS];
+  // table entries travel through registers two blocks ahead of their use
+  uint32_t off[KS], off1[KS];
+  float wgt[KS], wgt1[KS];
 #pragma unroll
   for (int s4 = 0; s4 < KS; ++s4) {
     off[s4] = bo[s4 * kWave + lane];
     wgt[s4] = bw[s4 * kWave + lane];
+    off1[s4] = bo[bstride + s4 * kWave + lane];
+    wgt1[s4] = bw[bstride + s4 * kWave + lane];
   }
+  bo += bstride;
+  bw += bstride;
   int since = 0;
   const char* yrow = smem + laneoff;
   for (int b = b0; b < nblk; ++b) {
@@ -249,8 +254,10 @@ __device__ __forceinline__ void gather_library(const char* smem, const uint32_t*
     }
 #pragma unroll
     for (int s4 = 0; s4 < KS; ++s4) {
-      off[s4] = offn[s4];
-      wgt[s4] = wgtn[s4];
+      off[s4] = off1[s4];
+      wgt[s4] = wgt1[s4];
+      off1[s4] = offn[s4];
+      wgt1[s4] = wgtn[s4];
     }
   }
   fold(m);

@@ -136,8 +136,10 @@ __global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
   const int lane = lane_id();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int half = wave & 1;     // rows 64*half .. 64*half+63 of each 128-row chunk
-  const int j0 = blockIdx.x * kBTN;
-  const int li = blockIdx.y * 2 + (wave >> 1);
+  // blockIdx.x = library pair (fastest), blockIdx.y = target tile: the workgroups resident
+  // at one time share a target tile, whose BF16 and FP32 columns then stay in L2
+  const int j0 = blockIdx.y * kBTN;
+  const int li = blockIdx.x * 2 + (wave >> 1);
   const bool has = li < n_lib;
   const int i = has ? __builtin_amdgcn_readfirstlane(order[li]) : 0;
   const int k = has ? __builtin_amdgcn_readfirstlane(lib_k[i]) : 0;
@@ -181,10 +183,13 @@ __global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
       for (int q = half * kWave + lane; q <= nst; q += 2 * kWave) so[q] = sg[q];
       for (int q = half * kWave + lane; q < ne; q += 2 * kWave) eo[q] = eg[q];
     }
-    uint4 breg[4];
+    // B stages travel through registers two stages ahead of their use
+    uint4 breg[4], breg2[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 4; ++q) {
       breg[q] = brow_ok ? *(const uint4*)(ysrc + q * 8) : uint4{0, 0, 0, 0};
+      breg2[q] = (brow_ok && nst > 1) ? *(const uint4*)(ysrc + kStage + q * 8) : uint4{0, 0, 0, 0};
+    }
     __syncthreads();  // staged entries visible to both waves of each library
     for (int st = 0; st < nst; ++st) {
       const int buf = st & 1;
@@ -205,11 +210,12 @@ __global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
         for (int q = 0; q < 4; ++q) *(uint4*)(dst + q * 8) = breg[q];
       }
       __syncthreads();  // B stage `buf` complete; the other buffer is free
-      if (st + 1 < nst) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          breg[q] = brow_ok ? *(const uint4*)(ysrc + (size_t)(st + 1) * kStage + q * 8)
-                            : uint4{0, 0, 0, 0};
+      for (int q = 0; q < 4; ++q) {
+        breg[q] = breg2[q];
+        breg2[q] = (brow_ok && st + 2 < nst)
+                       ? *(const uint4*)(ysrc + (size_t)(st + 2) * kStage + q * 8)
+                       : uint4{0, 0, 0, 0};
       }
       if (e1 > e0) {
         const uint16_t* Bb = Bs + (size_t)buf * kBTN * kStage;
@@ -330,7 +336,7 @@ extern "C" hipError_t ccm_launch_crossmap_bf16(const float* ts, int64_t ld, int 
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(ccm::gather_bf16_kernel, dim3((n_tgt + ccm::kBTN - 1) / ccm::kBTN, (n_lib + 1) / 2),
+  hipLaunchKernelGGL(ccm::gather_bf16_kernel, dim3((n_lib + 1) / 2, (n_tgt + ccm::kBTN - 1) / ccm::kBTN),
                      dim3(ccm::kBThreads), ccm_bf16_lds_bytes(), stream, ts, ld, L, tau, tgt0, n_tgt,
                      Lpad, yt, ent, stage_off, order, lib_k, n_lib, nchunk_max, nst, rho, moments);
   return hipGetLastError();
