@@ -139,16 +139,28 @@ __global__ __launch_bounds__(256) void prep_tables_kernel(
 // ---------------------------------------------------------------------------------------
 // acc.xyzw += bcast_M(w) * y.xyzw, the weight broadcast inside the quad folded into the
 // FMAs as a DPP operand.  The leading s_nop covers the DPP read-after-VALU-write hazard.
-template <int M>
+// FIRST: acc = bcast_M(w) * y (no accumulator to clear).
+template <int M, bool FIRST>
 __device__ __forceinline__ void fma4_bcast(float4& acc, float w, const float4& y) {
-  asm volatile(
-      "s_nop 1\n\t"
-      "v_fmac_f32_dpp %0, %4, %5 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_fmac_f32_dpp %1, %4, %6 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_fmac_f32_dpp %2, %4, %7 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_fmac_f32_dpp %3, %4, %9 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1"
-      : "+v"(acc.x), "+v"(acc.y), "+v"(acc.z), "+v"(acc.w)
-      : "v"(w), "v"(y.x), "v"(y.y), "v"(y.z), "n"(M), "v"(y.w));
+  if constexpr (FIRST) {
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_mul_f32_dpp %0, %4, %5 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_mul_f32_dpp %1, %4, %6 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_mul_f32_dpp %2, %4, %7 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_mul_f32_dpp %3, %4, %9 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "=&v"(acc.x), "=&v"(acc.y), "=&v"(acc.z), "=&v"(acc.w)
+        : "v"(w), "v"(y.x), "v"(y.y), "v"(y.z), "n"(M), "v"(y.w));
+  } else {
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_fmac_f32_dpp %0, %4, %5 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %4, %6 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %2, %4, %7 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %3, %4, %9 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "+v"(acc.x), "+v"(acc.y), "+v"(acc.z), "+v"(acc.w)
+        : "v"(w), "v"(y.x), "v"(y.y), "v"(y.z), "n"(M), "v"(y.w));
+  }
 }
 
 // Steps J .. J+3 of one table row: the four 128-bit LDS reads are issued before any of
@@ -170,10 +182,10 @@ __device__ __forceinline__ void gather_quad(const char* tile, const uint32_t (&o
       y[q] = *(const float4*)(tile + o + laneoff);
     }
   }
-  if (J + 0 < K) fma4_bcast<0>(acc, wgt[S], y[0]);
-  if (J + 1 < K) fma4_bcast<1>(acc, wgt[S], y[1]);
-  if (J + 2 < K) fma4_bcast<2>(acc, wgt[S], y[2]);
-  if (J + 3 < K) fma4_bcast<3>(acc, wgt[S], y[3]);
+  if (J + 0 < K) fma4_bcast<0, J == 0>(acc, wgt[S], y[0]);
+  if (J + 1 < K) fma4_bcast<1, false>(acc, wgt[S], y[1]);
+  if (J + 2 < K) fma4_bcast<2, false>(acc, wgt[S], y[2]);
+  if (J + 3 < K) fma4_bcast<3, false>(acc, wgt[S], y[3]);
 }
 
 template <int K, int J = 0>
@@ -201,6 +213,36 @@ __device__ __forceinline__ void fold(Moments& m) {
 // One library against the tile: 16 query times per block step, all K products unrolled,
 // next block's table entries loaded while this one is summed.  Rows outside the query
 // range carry weight 0 (prediction exactly 0), so they add nothing to the moments.
+// One block step: 16 query times of one library against the tile, then the moments.
+// Rows outside the query range carry weight 0 (prediction exactly 0), so they add nothing.
+template <int K>
+__device__ __forceinline__ void gather_block(const char* smem, const uint32_t (&off)[(K + 3) / 4],
+                                             const float (&wgt)[(K + 3) / 4], uint32_t laneoff,
+                                             int t, int L, Moments& m) {
+  float4 acc;
+  gather_row<K>(smem, off, wgt, laneoff, acc);
+  t = t < L ? t : L - 1;
+  const float4 yo = *(const float4*)(smem + laneoff + (uint32_t)t * kRowBytes);
+  m.sp.x += acc.x; m.sp.y += acc.y; m.sp.z += acc.z; m.sp.w += acc.w;
+  m.spp.x = fmaf(acc.x, acc.x, m.spp.x); m.spp.y = fmaf(acc.y, acc.y, m.spp.y);
+  m.spp.z = fmaf(acc.z, acc.z, m.spp.z); m.spp.w = fmaf(acc.w, acc.w, m.spp.w);
+  m.syp.x = fmaf(yo.x, acc.x, m.syp.x); m.syp.y = fmaf(yo.y, acc.y, m.syp.y);
+  m.syp.z = fmaf(yo.z, acc.z, m.syp.z); m.syp.w = fmaf(yo.w, acc.w, m.syp.w);
+}
+
+template <int KS>
+__device__ __forceinline__ void load_slots(const uint32_t* bo, const float* bw, int lane,
+                                           uint32_t (&off)[KS], float (&wgt)[KS]) {
+#pragma unroll
+  for (int s4 = 0; s4 < KS; ++s4) {
+    off[s4] = bo[s4 * kWave + lane];
+    wgt[s4] = bw[s4 * kWave + lane];
+  }
+}
+
+// One library against the tile.  Block steps run in pairs with two register sets, each
+// loaded two steps ahead of its use (no register copies); FP32 moment sums are folded
+// into FP64 every 8 steps.
 template <int K>
 __device__ __forceinline__ void gather_library(const char* smem, const uint32_t* __restrict__ po,
                                                const float* __restrict__ pq, int b0, int nblk,
@@ -210,57 +252,39 @@ __device__ __forceinline__ void gather_library(const char* smem, const uint32_t*
   const int lane = lane_id();
   const size_t bstride = (size_t)KSM * kWave;   // entries per block
   // block pointers are uniform (scalar base + lane offset + immediate slot offset); the
-  // workspace holds two spare blocks after the last library, so the prefetch of block b + 2
-  // is always in bounds
+  // workspace holds two spare blocks after the last library, so loads of blocks b + 1 and
+  // b + 2 are always in bounds
   const uint32_t* bo = po + (size_t)b0 * bstride;
   const float* bw = pq + (size_t)b0 * bstride;
-  // table entries travel through registers two blocks ahead of their use
-  uint32_t off[KS], off1[KS];
-  float wgt[KS], wgt1[KS];
+  uint32_t offA[KS], offB[KS];
+  float wgtA[KS], wgtB[KS];
+  load_slots<KS>(bo, bw, lane, offA, wgtA);
+  load_slots<KS>(bo + bstride, bw + bstride, lane, offB, wgtB);
+  int b = b0;
+  while (b < nblk) {
+    const int bend = b + 8 < nblk ? b + 8 : nblk;
+    for (; b + 1 < bend; b += 2) {
+      gather_block<K>(smem, offA, wgtA, laneoff, b * 16 + G, L, m);
+      load_slots<KS>(bo + 2 * bstride, bw + 2 * bstride, lane, offA, wgtA);
+      gather_block<K>(smem, offB, wgtB, laneoff, (b + 1) * 16 + G, L, m);
+      load_slots<KS>(bo + 3 * bstride, bw + 3 * bstride, lane, offB, wgtB);
+      bo += 2 * bstride;
+      bw += 2 * bstride;
+    }
+    if (b < bend) {  // odd tail of this group: one step, then swap the register roles
+      gather_block<K>(smem, offA, wgtA, laneoff, b * 16 + G, L, m);
+      load_slots<KS>(bo + 2 * bstride, bw + 2 * bstride, lane, offA, wgtA);
+      bo += bstride;
+      bw += bstride;
+      ++b;
 #pragma unroll
-  for (int s4 = 0; s4 < KS; ++s4) {
-    off[s4] = bo[s4 * kWave + lane];
-    wgt[s4] = bw[s4 * kWave + lane];
-    off1[s4] = bo[bstride + s4 * kWave + lane];
-    wgt1[s4] = bw[bstride + s4 * kWave + lane];
+      for (int s4 = 0; s4 < KS; ++s4) {
+        const uint32_t to = offA[s4]; offA[s4] = offB[s4]; offB[s4] = to;
+        const float tw = wgtA[s4]; wgtA[s4] = wgtB[s4]; wgtB[s4] = tw;
+      }
+    }
+    fold(m);
   }
-  bo += bstride;
-  bw += bstride;
-  int since = 0;
-  const char* yrow = smem + laneoff;
-  for (int b = b0; b < nblk; ++b) {
-    bo += bstride;
-    bw += bstride;
-    uint32_t offn[KS];
-    float wgtn[KS];
-#pragma unroll
-    for (int s4 = 0; s4 < KS; ++s4) {
-      offn[s4] = bo[s4 * kWave + lane];
-      wgtn[s4] = bw[s4 * kWave + lane];
-    }
-    float4 acc = {0, 0, 0, 0};
-    gather_row<K>(smem, off, wgt, laneoff, acc);
-    int t = b * 16 + G;
-    t = t < L ? t : L - 1;
-    const float4 yo = *(const float4*)(yrow + (uint32_t)t * kRowBytes);
-    m.sp.x += acc.x; m.sp.y += acc.y; m.sp.z += acc.z; m.sp.w += acc.w;
-    m.spp.x = fmaf(acc.x, acc.x, m.spp.x); m.spp.y = fmaf(acc.y, acc.y, m.spp.y);
-    m.spp.z = fmaf(acc.z, acc.z, m.spp.z); m.spp.w = fmaf(acc.w, acc.w, m.spp.w);
-    m.syp.x = fmaf(yo.x, acc.x, m.syp.x); m.syp.y = fmaf(yo.y, acc.y, m.syp.y);
-    m.syp.z = fmaf(yo.z, acc.z, m.syp.z); m.syp.w = fmaf(yo.w, acc.w, m.syp.w);
-    if (++since == 8) {
-      since = 0;
-      fold(m);
-    }
-#pragma unroll
-    for (int s4 = 0; s4 < KS; ++s4) {
-      off[s4] = off1[s4];
-      wgt[s4] = wgt1[s4];
-      off1[s4] = offn[s4];
-      wgt1[s4] = wgtn[s4];
-    }
-  }
-  fold(m);
 }
 
 __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(

@@ -37,6 +37,9 @@ constexpr int kBTN = 128;     // targets per tile
 constexpr int kBRows = 128;   // rows of A per chunk
 constexpr int kHalf = 64;     // rows of A per wave
 constexpr int kStage = 64;    // K per stage
+// LDS row stride of the A and B tiles in BF16 elements: 64 + 8 pad, so the 16 rows read
+// by one 16-lane pass of a 128-bit fragment load start 36 banks apart and never collide
+constexpr int kRS = kStage + 8;
 constexpr int kBThreads = 256;
 constexpr int kMaxStages = 16384 / kStage;  // L <= 16384
 
@@ -128,8 +131,8 @@ __global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
   // B: two stages of Yt [128 targets][64 s] BF16 (16 KB each); A: per wave [64 rows][64 s];
   // moments: per wave [5][4][64] FP64.
   uint16_t* Bs = (uint16_t*)smem;
-  uint16_t* As = (uint16_t*)(smem + 2 * kBTN * kStage * 2);
-  double* momb = (double*)(smem + 2 * kBTN * kStage * 2 + 4 * kHalf * kStage * 2);
+  uint16_t* As = (uint16_t*)(smem + 2 * kBTN * kRS * 2);
+  double* momb = (double*)(smem + 2 * kBTN * kRS * 2 + 4 * kHalf * kRS * 2);
   // the current chunk's sorted entries and stage offsets of both libraries
   uint32_t* Es = (uint32_t*)(momb + 4 * 5 * 4 * kWave);
   int* Ss = (int*)(Es + 2 * kBRows * kKMax);
@@ -149,8 +152,8 @@ __global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
   const int nchunk = (nrows + kBRows - 1) / kBRows;
   __shared__ int s_nchunk[4];
   if (lane == 0) s_nchunk[wave] = nchunk;
-  uint16_t* Aw = As + (size_t)wave * kHalf * kStage;
-  for (int q = lane; q < kHalf * kStage / 2; q += kWave) ((uint32_t*)Aw)[q] = 0u;
+  uint16_t* Aw = As + (size_t)wave * kHalf * kRS;
+  for (int q = lane; q < kHalf * kRS / 2; q += kWave) ((uint32_t*)Aw)[q] = 0u;
   double* mom = momb + (size_t)wave * 5 * 4 * kWave;
 #pragma unroll
   for (int q = 0; q < 20; ++q) mom[q * kWave + lane] = 0.0;
@@ -202,10 +205,10 @@ __global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
       for (int e = e0 + lane; e < e1; e += kWave) {
         const uint32_t v = eo[e];
         const int row = v & 127;
-        if ((row >> 6) == half) Aw[(row & 63) * kStage + ((v >> 7) & 63)] = (uint16_t)(v >> 16);
+        if ((row >> 6) == half) Aw[(row & 63) * kRS + ((v >> 7) & 63)] = (uint16_t)(v >> 16);
       }
       {
-        uint16_t* dst = Bs + (size_t)buf * kBTN * kStage + br * kStage + bh * 32;
+        uint16_t* dst = Bs + (size_t)buf * kBTN * kRS + br * kRS + bh * 32;
 #pragma unroll
         for (int q = 0; q < 4; ++q) *(uint4*)(dst + q * 8) = breg[q];
       }
@@ -218,16 +221,16 @@ __global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
                        : uint4{0, 0, 0, 0};
       }
       if (e1 > e0) {
-        const uint16_t* Bb = Bs + (size_t)buf * kBTN * kStage;
+        const uint16_t* Bb = Bs + (size_t)buf * kBTN * kRS;
 #pragma unroll
         for (int kk = 0; kk < kStage / 16; ++kk) {
           bf16x8 af[2], bfr[4];
 #pragma unroll
           for (int a = 0; a < 2; ++a)
-            af[a] = *(const bf16x8*)(Aw + (32 * a + (lane & 31)) * kStage + 16 * kk + 8 * (lane >> 5));
+            af[a] = *(const bf16x8*)(Aw + (32 * a + (lane & 31)) * kRS + 16 * kk + 8 * (lane >> 5));
 #pragma unroll
           for (int b = 0; b < 4; ++b)
-            bfr[b] = *(const bf16x8*)(Bb + (32 * b + (lane & 31)) * kStage + 16 * kk + 8 * (lane >> 5));
+            bfr[b] = *(const bf16x8*)(Bb + (32 * b + (lane & 31)) * kRS + 16 * kk + 8 * (lane >> 5));
 #pragma unroll
           for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -239,7 +242,7 @@ __global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
       for (int e = e0 + lane; e < e1; e += kWave) {
         const uint32_t v = eo[e];
         const int row = v & 127;
-        if ((row >> 6) == half) Aw[(row & 63) * kStage + ((v >> 7) & 63)] = 0;
+        if ((row >> 6) == half) Aw[(row & 63) * kRS + ((v >> 7) & 63)] = 0;
       }
     }
     // epilogue: moments of this chunk's rows
@@ -308,7 +311,7 @@ __global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
 extern "C" hipError_t ccm_launch_order(const int* lib_k, int n_lib, int* order, hipStream_t stream);
 
 extern "C" size_t ccm_bf16_lds_bytes() {
-  return 2 * (size_t)ccm::kBTN * ccm::kStage * 2 + 4 * (size_t)ccm::kHalf * ccm::kStage * 2 +
+  return 2 * (size_t)ccm::kBTN * ccm::kRS * 2 + 4 * (size_t)ccm::kHalf * ccm::kRS * 2 +
          4 * 5 * 4 * (size_t)ccm::kWave * sizeof(double) +
          2 * (size_t)ccm::kBRows * ccm::kKMax * 4 + 2 * (size_t)(ccm::kMaxStages + 1) * 4;
 }
