@@ -163,39 +163,47 @@ __device__ __forceinline__ void fma4_bcast(float4& acc, float w, const float4& y
   }
 }
 
-// Steps J .. J+3 of one table row: the four 128-bit LDS reads are issued before any of
-// their products, so several reads are in flight per wave.
+// Reads of steps J, J+1 of one table row (128-bit LDS reads, one per step).
 template <int J, int K>
-__device__ __forceinline__ void gather_quad(const char* tile, const uint32_t (&off)[(K + 3) / 4],
-                                            const float (&wgt)[(K + 3) / 4], uint32_t laneoff,
-                                            float4& acc) {
+__device__ __forceinline__ void pair_reads(const char* tile, const uint32_t (&off)[(K + 3) / 4],
+                                           uint32_t laneoff, float4 (&y)[2]) {
   constexpr int S = J >> 2;
-  float4 y[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    if (J + q < K) {
-      uint32_t o;
-      if (q == 0) o = (uint32_t)quad_bcast<0>((int)off[S]);
-      if (q == 1) o = (uint32_t)quad_bcast<1>((int)off[S]);
-      if (q == 2) o = (uint32_t)quad_bcast<2>((int)off[S]);
-      if (q == 3) o = (uint32_t)quad_bcast<3>((int)off[S]);
-      y[q] = *(const float4*)(tile + o + laneoff);
-    }
-  }
-  if (J + 0 < K) fma4_bcast<0, J == 0>(acc, wgt[S], y[0]);
-  if (J + 1 < K) fma4_bcast<1, false>(acc, wgt[S], y[1]);
-  if (J + 2 < K) fma4_bcast<2, false>(acc, wgt[S], y[2]);
-  if (J + 3 < K) fma4_bcast<3, false>(acc, wgt[S], y[3]);
+  if (J + 0 < K)
+    y[0] = *(const float4*)(tile + (uint32_t)quad_bcast<(J & 3)>((int)off[S]) + laneoff);
+  if (J + 1 < K)
+    y[1] = *(const float4*)(tile + (uint32_t)quad_bcast<((J + 1) & 3)>((int)off[S]) + laneoff);
 }
 
+// Products of steps J, J+1.
+template <int J, int K>
+__device__ __forceinline__ void pair_fmas(const float (&wgt)[(K + 3) / 4], const float4 (&y)[2],
+                                          float4& acc) {
+  constexpr int S = J >> 2;
+  if (J + 0 < K) fma4_bcast<(J & 3), J == 0>(acc, wgt[S], y[0]);
+  if (J + 1 < K) fma4_bcast<((J + 1) & 3), false>(acc, wgt[S], y[1]);
+}
+
+// One table row, software-pipelined by pairs of steps: the reads of pair p+1 are issued
+// before the products of pair p, so each wave keeps up to four 128-bit LDS reads in flight.
 template <int K, int J = 0>
+__device__ __forceinline__ void gather_row_pipe(const char* tile,
+                                                const uint32_t (&off)[(K + 3) / 4],
+                                                const float (&wgt)[(K + 3) / 4], uint32_t laneoff,
+                                                float4 (&ya)[2], float4 (&yb)[2], float4& acc) {
+  if constexpr (J < K) {
+    if constexpr (J + 2 < K) pair_reads<J + 2, K>(tile, off, laneoff, yb);
+    pair_fmas<J, K>(wgt, ya, acc);
+    gather_row_pipe<K, J + 2>(tile, off, wgt, laneoff, yb, ya, acc);
+  }
+}
+
+template <int K>
 __device__ __forceinline__ void gather_row(const char* tile, const uint32_t (&off)[(K + 3) / 4],
                                            const float (&wgt)[(K + 3) / 4], uint32_t laneoff,
                                            float4& acc) {
-  if constexpr (J < K) {
-    gather_quad<J, K>(tile, off, wgt, laneoff, acc);
-    gather_row<K, J + 4>(tile, off, wgt, laneoff, acc);
-  }
+  float4 ya[2], yb[2];
+  pair_reads<0, K>(tile, off, laneoff, ya);
+  gather_row_pipe<K>(tile, off, wgt, laneoff, ya, yb, acc);
 }
 
 struct Moments {
