@@ -137,29 +137,18 @@ __global__ __launch_bounds__(256) void prep_tables_kernel(
 // The gather.  grid = (target tiles, library splits), block = 1024 threads.
 // LDS: tile [L][16] floats, then column sums sy[E][16], syy[E][16] (FP64, E = 1..20).
 // ---------------------------------------------------------------------------------------
-// acc.xyzw += bcast_M(w) * y.xyzw, the weight broadcast inside the quad folded into the
-// FMAs as a DPP operand.  The leading s_nop covers the DPP read-after-VALU-write hazard.
+// acc.xyzw += bcast_M(w) * y.xyzw: one DPP broadcast of the weight inside the quad, then
+// plain FMAs (a DPP-modified VALU op issues at about half the rate of a plain one on
+// gfx950, so the broadcast is done once per step, not once per product).
 // FIRST: acc = bcast_M(w) * y (no accumulator to clear).
 template <int M, bool FIRST>
 __device__ __forceinline__ void fma4_bcast(float4& acc, float w, const float4& y) {
+  const float wb = quad_bcast<M>(w);
   if constexpr (FIRST) {
-    asm volatile(
-        "s_nop 1\n\t"
-        "v_mul_f32_dpp %0, %4, %5 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-        "v_mul_f32_dpp %1, %4, %6 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-        "v_mul_f32_dpp %2, %4, %7 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-        "v_mul_f32_dpp %3, %4, %9 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1"
-        : "=&v"(acc.x), "=&v"(acc.y), "=&v"(acc.z), "=&v"(acc.w)
-        : "v"(w), "v"(y.x), "v"(y.y), "v"(y.z), "n"(M), "v"(y.w));
+    acc.x = wb * y.x; acc.y = wb * y.y; acc.z = wb * y.z; acc.w = wb * y.w;
   } else {
-    asm volatile(
-        "s_nop 1\n\t"
-        "v_fmac_f32_dpp %0, %4, %5 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-        "v_fmac_f32_dpp %1, %4, %6 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-        "v_fmac_f32_dpp %2, %4, %7 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-        "v_fmac_f32_dpp %3, %4, %9 quad_perm:[%8,%8,%8,%8] row_mask:0xf bank_mask:0xf bound_ctrl:1"
-        : "+v"(acc.x), "+v"(acc.y), "+v"(acc.z), "+v"(acc.w)
-        : "v"(w), "v"(y.x), "v"(y.y), "v"(y.z), "n"(M), "v"(y.w));
+    acc.x = fmaf(wb, y.x, acc.x); acc.y = fmaf(wb, y.y, acc.y);
+    acc.z = fmaf(wb, y.z, acc.z); acc.w = fmaf(wb, y.w, acc.w);
   }
 }
 
