@@ -60,13 +60,17 @@ __device__ __forceinline__ void list_insert(uint64_t& key, uint64_t kv) {
 }
 
 // Offer this chunk's candidate keys (~0 where not admissible) to one list whose k-th entry
-// sits in lane k1; `thr` is that entry's key.  Survivors are inserted one at a time.
+// sits in lane k1; `thr` is that entry's key.  Survivors are inserted one at a time; a key
+// already in the list (a seed met again by the scan) is skipped.
 __device__ __forceinline__ void offer_chunk(uint64_t cand, uint64_t& key, uint64_t& thr, int k1) {
   uint64_t m = ballot(cand < thr);
   while (m) {
     const int src = __ffsll((unsigned long long)m) - 1;
-    list_insert(key, readlane(cand, src));
-    thr = readlane(key, k1);
+    const uint64_t kv = readlane(cand, src);
+    if (ballot(key == kv) == 0) {
+      list_insert(key, kv);
+      thr = readlane(key, k1);
+    }
     m &= (~0ull << src) << 1;
     m &= ballot(cand < thr);
   }
@@ -104,6 +108,50 @@ __device__ __forceinline__ void lag_values(const float* x, int sc, int tau, floa
   }
 }
 
+// Build a sorted list from the distinct candidate keys in lanes 0..k1 (~0 where empty):
+// a key's rank among them is its lane in the list (equal empty keys are ranked by lane), and
+// a forward permute moves it there; lanes past k1 read ~0.
+__device__ __forceinline__ void list_from_keys(uint64_t cand, int k1, uint64_t& key,
+                                               uint64_t& thr) {
+  const int lane = lane_id();
+  int rank = 0;
+  for (int j = 0; j <= k1; ++j) {
+    const uint64_t kj = readlane(cand, j);
+    rank += (kj < cand || (kj == cand && j < lane)) ? 1 : 0;
+  }
+  const bool mine = lane <= k1;
+  const int dst = (mine ? rank : lane) << 2;
+  const uint64_t v = mine ? cand : ~0ull;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_permute(dst, (int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_permute(dst, (int)(uint32_t)(v >> 32));
+  key = ((uint64_t)hi << 32) | lo;
+  thr = readlane(key, k1);
+}
+
+// Seed a list for query t from the previous query's list: its neighbours shifted one step
+// forward are admissible candidates (with their canonical d^2 at this E) and usually lie
+// close to t's true neighbours, so the k-th distance starts tight and the scan that
+// follows inserts few candidates.  `key` holds the previous query's list (lanes 0..E) on
+// entry and the seeded list on exit.  Candidates run to `chi`; (E-1)*tau is the first.
+template <int E, bool TAU1, int NQ>
+__device__ __forceinline__ void seed_list(const float* x, int t, int tau, int chi, bool excl_self,
+                                          const float (&xq)[NQ], uint64_t& key, uint64_t& thr) {
+  const int lane = lane_id();
+  const int nb = lane <= E ? key_idx(key) : -1;
+  const int s = nb + 1;
+  const bool ok = nb >= 0 && s <= chi && (!excl_self || s != t);
+  const int sc = ok ? s : (E - 1) * tau;
+  float xs[E];
+  lag_values<E, TAU1>(x, sc, tau, xs);
+  float acc = 0.0f;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const float df = xq[e] - xs[e];
+    acc = acc + df * df;
+  }
+  list_from_keys(ok ? nkey(acc, s) : ~0ull, E, key, thr);
+}
+
 // Simplex weights of a finished list (lanes 0..k-1 hold neighbour n_j of query t).  The
 // distance of each selected neighbour is recomputed in FP64 from the series (k x E terms,
 // negligible next to the scan), so the weights do not depend on FP32 rounding or
@@ -127,27 +175,31 @@ __device__ __forceinline__ double list_weight64(const float* x, int t, int nb, i
   return u;
 }
 
-// ---------------------------------------------------------------------------------------
-// Neighbour tables at each library's own E (one launch for every E).
-// grid.x = n_lib, block = 1024 (16 waves, one query each at a time); LDS: the series.
-// ---------------------------------------------------------------------------------------
 constexpr int kKnnThreads = 1024;
 
 // The scan of one query at a compile-time E: every candidate chunk's lag reads are issued
-// together, then the canonical d^2 is formed in lag order.
+// together, then the canonical d^2 is formed in lag order.  With `seeded`, key/thr are
+// seeded from the previous query's list and all chunks are scanned in order; otherwise the
+// list starts empty and the window around t is scanned first.
 template <int E, bool TAU1>
 __device__ __forceinline__ void knn_query(const float* x, int t, int lo, int hi, int tau,
-                                          float& ldist, int& lidx) {
+                                          bool seeded, uint64_t& key, uint64_t& thr) {
   const int lane = lane_id();
-  float xq[E];
+  float xq[kEMax];
 #pragma unroll
-  for (int e = 0; e < E; ++e)
-    xq[e] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x[t - e * tau])));
-  uint64_t key = ~0ull;
-  uint64_t thr = ~0ull;
-  const int wb = window_base(t, lo, hi);
-  // pass -1: the window around t; then every chunk in order, skipping the window
-  for (int pass = -1, base = lo; base <= hi; base += (pass < 0 ? 0 : kWave), pass = 0) {
+  for (int e = 0; e < kEMax; ++e)
+    xq[e] = e < E ? __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x[t - e * tau])))
+                  : 0.0f;
+  if (seeded) {
+    seed_list<E, TAU1, kEMax>(x, t, tau, hi, true, xq, key, thr);
+  } else {
+    key = ~0ull;
+    thr = ~0ull;
+  }
+  const int wb = seeded ? hi + 1 : window_base(t, lo, hi);
+  // pass -1: the window around t (unseeded only); then every chunk in order
+  for (int pass = seeded ? 0 : -1, base = lo; base <= hi;
+       base += (pass < 0 ? 0 : kWave), pass = 0) {
     const int b = pass < 0 ? wb : base;
     const int s = b + lane;
     const bool inr = s <= hi && (pass < 0 || s < wb || s >= wb + kWave);
@@ -163,8 +215,6 @@ __device__ __forceinline__ void knn_query(const float* x, int t, int lo, int hi,
     const uint64_t cand = (inr && s != t) ? nkey(acc, s) : ~0ull;
     offer_chunk(cand, key, thr, E);
   }
-  ldist = key_d2(key);
-  lidx = key_idx(key);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -195,43 +245,48 @@ __global__ __launch_bounds__(kKnnThreads) void knn_table_kernel(const float* __r
   const bool ok = E >= 1 && E <= kEMax && k <= k_max && (hi - lo + 1) - 1 >= k;
   const size_t rowbase = (size_t)lib * L;
 
+  // padding rows (outside [lo, hi], or every row of an unusable library)
   for (int t = wave; t < L; t += nw) {
-    int* oi = nbr_idx + (rowbase + t) * k_max;
-    float* ow = nbr_w + (rowbase + t) * k_max;
-    float* od = nbr_d2 ? nbr_d2 + (rowbase + t) * k_max : nullptr;
-    if (!ok || t < lo || t > hi) {
-      if (lane < k_max) {
-        oi[lane] = -1;
-        ow[lane] = 0.0f;
-        if (od) od[lane] = INFINITY;
-      }
-      continue;
+    if (ok && t >= lo && t <= hi) continue;
+    if (lane < k_max) {
+      nbr_idx[(rowbase + t) * k_max + lane] = -1;
+      nbr_w[(rowbase + t) * k_max + lane] = 0.0f;
+      if (nbr_d2) nbr_d2[(rowbase + t) * k_max + lane] = INFINITY;
     }
-    float ldist;
-    int lidx;
+  }
+  if (!ok) return;
+  // each wave walks a contiguous range of queries, seeding each list from the previous one
+  const int nq = hi - lo + 1;
+  const int per = (nq + nw - 1) / nw;
+  const int tb = lo + wave * per;
+  const int te = min(tb + per, hi + 1);
+  uint64_t key = ~0ull, thr = ~0ull;
+  for (int t = tb; t < te; ++t) {
+    const bool seeded = t > tb;
     switch (E) {
-#define CCM_E(EE)                                            \
-  case EE:                                                   \
-    if (tau == 1)                                            \
-      knn_query<EE, true>(x, t, lo, hi, tau, ldist, lidx);   \
-    else                                                     \
-      knn_query<EE, false>(x, t, lo, hi, tau, ldist, lidx);  \
+#define CCM_E(EE)                                                 \
+  case EE:                                                        \
+    if (tau == 1)                                                 \
+      knn_query<EE, true>(x, t, lo, hi, tau, seeded, key, thr);   \
+    else                                                          \
+      knn_query<EE, false>(x, t, lo, hi, tau, seeded, key, thr);  \
     break;
       CCM_E(1) CCM_E(2) CCM_E(3) CCM_E(4) CCM_E(5) CCM_E(6) CCM_E(7) CCM_E(8) CCM_E(9) CCM_E(10)
       CCM_E(11) CCM_E(12) CCM_E(13) CCM_E(14) CCM_E(15) CCM_E(16) CCM_E(17) CCM_E(18) CCM_E(19)
       CCM_E(20)
 #undef CCM_E
       default:
-        ldist = INFINITY;
-        lidx = -1;
+        break;
     }
+    const float ldist = key_d2(key);
+    const int lidx = key_idx(key);
     double usum;
-    double u = list_weight64(x, t, lidx, E, tau, k, usum);
+    double u = list_weight64(x, t, lane < k ? lidx : -1, E, tau, k, usum);
     if (lane < k_max) {
-      bool in = lane < k;
-      oi[lane] = in ? lidx : -1;
-      ow[lane] = in ? (float)(u / usum) : 0.0f;
-      if (od) od[lane] = in ? ldist : INFINITY;
+      const bool in = lane < k;
+      nbr_idx[(rowbase + t) * k_max + lane] = in ? lidx : -1;
+      nbr_w[(rowbase + t) * k_max + lane] = in ? (float)(u / usum) : 0.0f;
+      if (nbr_d2) nbr_d2[(rowbase + t) * k_max + lane] = in ? ldist : INFINITY;
     }
   }
 }
@@ -246,6 +301,22 @@ __global__ __launch_bounds__(kKnnThreads) void knn_table_kernel(const float* __r
 // ---------------------------------------------------------------------------------------
 constexpr int kSimplexThreads = 512;
 constexpr int kGroupE = 10;
+
+// Seed every list of the group that held a list at the previous query (t - 1 >= its first
+// query) from that list; lists starting at t begin empty.
+template <int ELO, int G, int NG, bool TAU1, int EHI>
+__device__ __forceinline__ void seed_group(const float* x, int t, int tau, int chi, bool half,
+                                           int qbase, int E_lo, int E_hi,
+                                           const float (&xq)[EHI], uint64_t (&key)[NG],
+                                           uint64_t (&thr)[NG]) {
+  if constexpr (G < NG) {
+    constexpr int E = ELO + G;
+    const int qE = qbase + (E - 1) * tau;
+    if (E >= E_lo && E <= E_hi && t - 1 >= qE)
+      seed_list<E, TAU1, EHI>(x, t, tau, chi, !half, xq, key[G], thr[G]);
+    seed_group<ELO, G + 1, NG, TAU1, EHI>(x, t, tau, chi, half, qbase, E_lo, E_hi, xq, key, thr);
+  }
+}
 
 template <int ELO, int EHI, bool TAU1>
 __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, int E_max, int tau,
@@ -265,20 +336,32 @@ __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, 
   // lane g holds the five FP64 moment sums of E = ELO + g
   double m_o = 0.0, m_oo = 0.0, m_p = 0.0, m_pp = 0.0, m_op = 0.0;
 
-  for (int t = qlo + wave; t <= qhi; t += nw) {
+  // each wave walks a contiguous range of queries; every list is carried from one query to
+  // the next and re-seeded with its shifted neighbours
+  const int nq = qhi - qlo + 1;
+  const int per = nq > 0 ? (nq + nw - 1) / nw : 0;
+  const int tb = qlo + wave * per;
+  const int te = min(tb + per, qhi + 1);
+  uint64_t key[NG];
+  uint64_t thr[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) key[g] = thr[g] = ~0ull;
+  for (int t = tb; t < te; ++t) {
     float xq[EHI];
 #pragma unroll
     for (int e = 0; e < EHI; ++e)
       xq[e] = __int_as_float(__builtin_amdgcn_readfirstlane(
           __float_as_int(t - e * tau >= 0 ? x[t - e * tau] : 0.0f)));
-    uint64_t key[NG];
-    uint64_t thr[NG];
-#pragma unroll
-    for (int g = 0; g < NG; ++g) key[g] = thr[g] = ~0ull;
-    // the window of candidates around t first (HALF mode: candidates are in the other
-    // half, so the window clamps to its end), then every chunk in order
-    const int wb = window_base(t, clo, chi);
-    for (int pass = -1, base = clo; base <= chi; base += (pass < 0 ? 0 : kWave), pass = 0) {
+    const bool seeded = t > tb;
+    if (seeded) seed_group<ELO, 0, NG, TAU1, EHI>(x, t, tau, chi, half, qbase, E_lo, E_hi, xq,
+                                                  key, thr);
+    // the window of candidates around t first when some list starts empty (HALF mode:
+    // candidates are in the other half, so the window clamps to its end), then every chunk
+    // in order
+    const bool win = !seeded || t - 1 < qbase + (E_hi - 1) * tau;
+    const int wb = win ? window_base(t, clo, chi) : chi + 1;
+    for (int pass = win ? -1 : 0, base = clo; base <= chi;
+         base += (pass < 0 ? 0 : kWave), pass = 0) {
       const int b = pass < 0 ? wb : base;
       const int s = b + lane;
       const bool inr = s <= chi && (pass < 0 || s < wb || s >= wb + kWave);
