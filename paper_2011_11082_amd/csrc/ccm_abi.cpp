@@ -65,7 +65,7 @@ CrossmapWs crossmap_ws(int L, int n_lib, int k_max) {
   CrossmapWs w;
   const size_t nblk = (size_t)(L + 15) / 16;
   const size_t KSM = (size_t)(k_max + 3) / 4;
-  // three spare blocks after the last library: the gather loads up to block b + 3 unguarded
+  // spare blocks after the last library: the gather prefetches block b + 1 unguarded
   const size_t ent = ((size_t)n_lib * nblk + 3) * KSM * 64;
   w.off_poff = 0;
   w.off_pw = align_up(w.off_poff + ent * 4);

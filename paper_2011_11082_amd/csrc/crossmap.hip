@@ -10,9 +10,11 @@
 //     (64 B per time step), loaded once from HBM and reused by every library it visits.
 //   * A wavefront works on one library at a time and 16 consecutive query times at once:
 //     lane = 4 * G + l, group G = query t0 + G, and lane l reads targets 4l..4l+3 of a
-//     neighbour row with one 128-bit LDS read.  The group's table entries arrive with one
+//     neighbour row with one 128-bit LDS read.  The group's LDS offsets arrive with one
 //     coalesced 256-byte load per four entries and are broadcast inside the quad by DPP
-//     (quad_perm), so no scalar or per-lane table traffic sits in the inner loop.
+//     (fused into the address add); its weights arrive as one 16-byte load per four entries
+//     from an address the quad shares, so each product is a plain FMA.  Each slot of four
+//     entries is reloaded for the next block as soon as its products are done.
 //   * LDS bank quarter of row s is s mod 4.  Four groups read in the same LDS pass
 //     (lanes 16m..16m+15, queries t = 0,1,2,3 mod 4); a preparation kernel orders each
 //     table row so that at step j query t prefers a neighbour with s = t + j (mod 4),
@@ -137,62 +139,25 @@ __global__ __launch_bounds__(256) void prep_tables_kernel(
 // The gather.  grid = (target tiles, library splits), block = 1024 threads.
 // LDS: tile [L][16] floats, then column sums sy[E][16], syy[E][16] (FP64, E = 1..20).
 // ---------------------------------------------------------------------------------------
-// acc.xyzw += bcast_M(w) * y.xyzw: one DPP broadcast of the weight inside the quad, then
-// plain FMAs (a DPP-modified VALU op issues at about half the rate of a plain one on
-// gfx950, so the broadcast is done once per step, not once per product).
-// FIRST: acc = bcast_M(w) * y (no accumulator to clear).
-template <int M, bool FIRST>
-__device__ __forceinline__ void fma4_bcast(float4& acc, float w, const float4& y) {
-  const float wb = quad_bcast<M>(w);
+// Weight of step 4s + M from the slot's float4 (all four lanes of a quad hold the same four
+// weights, so the products need no cross-lane broadcast).
+template <int M>
+__device__ __forceinline__ float wcomp(const float4& v) {
+  if constexpr (M == 0) return v.x;
+  else if constexpr (M == 1) return v.y;
+  else if constexpr (M == 2) return v.z;
+  else return v.w;
+}
+
+// acc.xyzw (+)= w * y.xyzw; FIRST: no accumulator to clear.
+template <bool FIRST>
+__device__ __forceinline__ void fma4(float4& acc, float wb, const float4& y) {
   if constexpr (FIRST) {
     acc.x = wb * y.x; acc.y = wb * y.y; acc.z = wb * y.z; acc.w = wb * y.w;
   } else {
     acc.x = fmaf(wb, y.x, acc.x); acc.y = fmaf(wb, y.y, acc.y);
     acc.z = fmaf(wb, y.z, acc.z); acc.w = fmaf(wb, y.w, acc.w);
   }
-}
-
-// Reads of steps J, J+1 of one table row (128-bit LDS reads, one per step).
-template <int J, int K>
-__device__ __forceinline__ void pair_reads(const char* tile, const uint32_t (&off)[(K + 3) / 4],
-                                           uint32_t laneoff, float4 (&y)[2]) {
-  constexpr int S = J >> 2;
-  if (J + 0 < K)
-    y[0] = *(const float4*)(tile + (uint32_t)quad_bcast<(J & 3)>((int)off[S]) + laneoff);
-  if (J + 1 < K)
-    y[1] = *(const float4*)(tile + (uint32_t)quad_bcast<((J + 1) & 3)>((int)off[S]) + laneoff);
-}
-
-// Products of steps J, J+1.
-template <int J, int K>
-__device__ __forceinline__ void pair_fmas(const float (&wgt)[(K + 3) / 4], const float4 (&y)[2],
-                                          float4& acc) {
-  constexpr int S = J >> 2;
-  if (J + 0 < K) fma4_bcast<(J & 3), J == 0>(acc, wgt[S], y[0]);
-  if (J + 1 < K) fma4_bcast<((J + 1) & 3), false>(acc, wgt[S], y[1]);
-}
-
-// One table row, software-pipelined by pairs of steps: the reads of pair p+1 are issued
-// before the products of pair p, so each wave keeps up to four 128-bit LDS reads in flight.
-template <int K, int J = 0>
-__device__ __forceinline__ void gather_row_pipe(const char* tile,
-                                                const uint32_t (&off)[(K + 3) / 4],
-                                                const float (&wgt)[(K + 3) / 4], uint32_t laneoff,
-                                                float4 (&ya)[2], float4 (&yb)[2], float4& acc) {
-  if constexpr (J < K) {
-    if constexpr (J + 2 < K) pair_reads<J + 2, K>(tile, off, laneoff, yb);
-    pair_fmas<J, K>(wgt, ya, acc);
-    gather_row_pipe<K, J + 2>(tile, off, wgt, laneoff, yb, ya, acc);
-  }
-}
-
-template <int K>
-__device__ __forceinline__ void gather_row(const char* tile, const uint32_t (&off)[(K + 3) / 4],
-                                           const float (&wgt)[(K + 3) / 4], uint32_t laneoff,
-                                           float4& acc) {
-  float4 ya[2], yb[2];
-  pair_reads<0, K>(tile, off, laneoff, ya);
-  gather_row_pipe<K>(tile, off, wgt, laneoff, ya, yb, acc);
 }
 
 struct Moments {
@@ -207,17 +172,58 @@ __device__ __forceinline__ void fold(Moments& m) {
   m.sp = m.spp = m.syp = float4{0, 0, 0, 0};
 }
 
-// One library against the tile: 16 query times per block step, all K products unrolled,
-// next block's table entries loaded while this one is summed.  Rows outside the query
-// range carry weight 0 (prediction exactly 0), so they add nothing to the moments.
-// One block step: 16 query times of one library against the tile, then the moments.
-// Rows outside the query range carry weight 0 (prediction exactly 0), so they add nothing.
+// Table entries of one block held by one lane: slot s covers steps 4s..4s+3.  Lane 4G + l
+// holds the LDS offset of step 4s + l of query G (broadcast inside the quad when the read
+// address is formed) and all four weights of the slot (one 16-byte load from an address the
+// quad shares, so the memory system fetches each weight once).
+template <int KS>
+struct Slots {
+  uint32_t off[KS];
+  float4 wgt[KS];
+};
+
+template <int S, int KS>
+__device__ __forceinline__ void load_slot(const uint32_t* bo, const float* bw, int lane,
+                                          Slots<KS>& e) {
+  e.off[S] = bo[S * kWave + lane];
+  e.wgt[S] = *(const float4*)(bw + S * kWave + (lane & ~3));
+}
+
+template <int J, int K>
+__device__ __forceinline__ void pair_reads(const char* tile, const Slots<(K + 3) / 4>& e,
+                                           uint32_t laneoff, float4 (&y)[2]) {
+  constexpr int S = J >> 2;
+  if (J + 0 < K)
+    y[0] = *(const float4*)(tile + (uint32_t)quad_bcast<(J & 3)>((int)e.off[S]) + laneoff);
+  if (J + 1 < K)
+    y[1] = *(const float4*)(tile + (uint32_t)quad_bcast<((J + 1) & 3)>((int)e.off[S]) + laneoff);
+}
+
+// One table row, software-pipelined by pairs of steps (reads of pair p+1 issued before the
+// products of pair p).  Once the products of a slot are done its registers are reloaded
+// with the same slot of the next block, a whole block ahead of use.
+template <int K, int J = 0>
+__device__ __forceinline__ void gather_row_pipe(const char* tile, Slots<(K + 3) / 4>& e,
+                                                const uint32_t* nbo, const float* nbw, int lane,
+                                                uint32_t laneoff, float4 (&ya)[2],
+                                                float4 (&yb)[2], float4& acc) {
+  if constexpr (J < K) {
+    constexpr int S = J >> 2;
+    if constexpr (J + 2 < K) pair_reads<J + 2, K>(tile, e, laneoff, yb);
+    fma4<J == 0>(acc, wcomp<(J & 3)>(e.wgt[S]), ya[0]);
+    if constexpr (J + 1 < K) fma4<false>(acc, wcomp<((J + 1) & 3)>(e.wgt[S]), ya[1]);
+    if constexpr ((J + 2) % 4 == 0 || J + 2 >= K) load_slot<S>(nbo, nbw, lane, e);
+    gather_row_pipe<K, J + 2>(tile, e, nbo, nbw, lane, laneoff, yb, ya, acc);
+  }
+}
+
 template <int K>
-__device__ __forceinline__ void gather_block(const char* smem, const uint32_t (&off)[(K + 3) / 4],
-                                             const float (&wgt)[(K + 3) / 4], uint32_t laneoff,
-                                             int t, int L, Moments& m) {
-  float4 acc;
-  gather_row<K>(smem, off, wgt, laneoff, acc);
+__device__ __forceinline__ void gather_block(const char* smem, Slots<(K + 3) / 4>& e,
+                                             const uint32_t* nbo, const float* nbw, int lane,
+                                             uint32_t laneoff, int t, int L, Moments& m) {
+  float4 acc, ya[2], yb[2];
+  pair_reads<0, K>(smem, e, laneoff, ya);
+  gather_row_pipe<K>(smem, e, nbo, nbw, lane, laneoff, ya, yb, acc);
   t = t < L ? t : L - 1;
   const float4 yo = *(const float4*)(smem + laneoff + (uint32_t)t * kRowBytes);
   m.sp.x += acc.x; m.sp.y += acc.y; m.sp.z += acc.z; m.sp.w += acc.w;
@@ -227,58 +233,36 @@ __device__ __forceinline__ void gather_block(const char* smem, const uint32_t (&
   m.syp.z = fmaf(yo.z, acc.z, m.syp.z); m.syp.w = fmaf(yo.w, acc.w, m.syp.w);
 }
 
-template <int KS>
-__device__ __forceinline__ void load_slots(const uint32_t* bo, const float* bw, int lane,
-                                           uint32_t (&off)[KS], float (&wgt)[KS]) {
-#pragma unroll
-  for (int s4 = 0; s4 < KS; ++s4) {
-    off[s4] = bo[s4 * kWave + lane];
-    wgt[s4] = bw[s4 * kWave + lane];
+template <int K, int S = 0>
+__device__ __forceinline__ void load_all(const uint32_t* bo, const float* bw, int lane,
+                                         Slots<(K + 3) / 4>& e) {
+  if constexpr (S < (K + 3) / 4) {
+    load_slot<S>(bo, bw, lane, e);
+    load_all<K, S + 1>(bo, bw, lane, e);
   }
 }
 
-// One library against the tile.  Block steps run in pairs with two register sets, each
-// loaded two steps ahead of its use (no register copies); FP32 moment sums are folded
-// into FP64 every 8 steps.
+// One library against the tile; FP32 moment sums are folded into FP64 every 8 blocks.  The
+// workspace holds spare blocks after the last library, so the load of block b + 1 is
+// always in bounds.
 template <int K>
 __device__ __forceinline__ void gather_library(const char* smem, const uint32_t* __restrict__ po,
                                                const float* __restrict__ pq, int b0, int nblk,
                                                int KSM, int L, int G, uint32_t laneoff,
                                                Moments& m) {
-  constexpr int KS = (K + 3) / 4;
   const int lane = lane_id();
-  const size_t bstride = (size_t)KSM * kWave;   // entries per block
-  // block pointers are uniform (scalar base + lane offset + immediate slot offset); the
-  // workspace holds two spare blocks after the last library, so loads of blocks b + 1 and
-  // b + 2 are always in bounds
+  const size_t bstride = (size_t)KSM * kWave;
   const uint32_t* bo = po + (size_t)b0 * bstride;
   const float* bw = pq + (size_t)b0 * bstride;
-  uint32_t offA[KS], offB[KS];
-  float wgtA[KS], wgtB[KS];
-  load_slots<KS>(bo, bw, lane, offA, wgtA);
-  load_slots<KS>(bo + bstride, bw + bstride, lane, offB, wgtB);
+  Slots<(K + 3) / 4> e;
+  load_all<K>(bo, bw, lane, e);
   int b = b0;
   while (b < nblk) {
     const int bend = b + 8 < nblk ? b + 8 : nblk;
-    for (; b + 1 < bend; b += 2) {
-      gather_block<K>(smem, offA, wgtA, laneoff, b * 16 + G, L, m);
-      load_slots<KS>(bo + 2 * bstride, bw + 2 * bstride, lane, offA, wgtA);
-      gather_block<K>(smem, offB, wgtB, laneoff, (b + 1) * 16 + G, L, m);
-      load_slots<KS>(bo + 3 * bstride, bw + 3 * bstride, lane, offB, wgtB);
-      bo += 2 * bstride;
-      bw += 2 * bstride;
-    }
-    if (b < bend) {  // odd tail of this group: one step, then swap the register roles
-      gather_block<K>(smem, offA, wgtA, laneoff, b * 16 + G, L, m);
-      load_slots<KS>(bo + 2 * bstride, bw + 2 * bstride, lane, offA, wgtA);
+    for (; b < bend; ++b) {
       bo += bstride;
       bw += bstride;
-      ++b;
-#pragma unroll
-      for (int s4 = 0; s4 < KS; ++s4) {
-        const uint32_t to = offA[s4]; offA[s4] = offB[s4]; offB[s4] = to;
-        const float tw = wgtA[s4]; wgtA[s4] = wgtB[s4]; wgtB[s4] = tw;
-      }
+      gather_block<K>(smem, e, bo, bw, lane, laneoff, b * 16 + G, L, m);
     }
     fold(m);
   }
@@ -424,7 +408,7 @@ extern "C" hipError_t ccm_launch_crossmap_fp32(const float* ts, int64_t ld, int 
   }
   const int n_tiles = (n_tgt + ccm::kTJ - 1) / ccm::kTJ;
   int splits = (1024 + n_tiles - 1) / n_tiles;
-  const int max_splits = (n_lib + 15) / 16;
+  const int max_splits = (n_lib + ccm::kGatherThreads / ccm::kWave - 1) / (ccm::kGatherThreads / ccm::kWave);
   if (splits > max_splits) splits = max_splits;
   if (splits < 1) splits = 1;
   hipLaunchKernelGGL(ccm::gather_fp32_kernel, dim3(n_tiles, splits), dim3(ccm::kGatherThreads), lds,
