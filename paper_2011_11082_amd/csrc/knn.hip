@@ -108,24 +108,30 @@ __device__ __forceinline__ void lag_values(const float* x, int sc, int tau, floa
   }
 }
 
-// Build a sorted list from the distinct candidate keys in lanes 0..k1 (~0 where empty):
-// a key's rank among them is its lane in the list (equal empty keys are ranked by lane), and
-// a forward permute moves it there; lanes past k1 read ~0.
+// Build a sorted list from the distinct candidate keys in lanes 0..k1 (~0 where empty): an
+// empty entry becomes ~0 - lane, so all k1 + 1 keys differ and stay above every real key
+// (their index reads negative); a key's rank among them is its lane in the list, and a
+// forward permute moves it there.  Lanes past k1 read ~0.
 __device__ __forceinline__ void list_from_keys(uint64_t cand, int k1, uint64_t& key,
                                                uint64_t& thr) {
   const int lane = lane_id();
-  int rank = 0;
-  for (int j = 0; j <= k1; ++j) {
-    const uint64_t kj = readlane(cand, j);
-    rank += (kj < cand || (kj == cand && j < lane)) ? 1 : 0;
-  }
   const bool mine = lane <= k1;
+  const uint64_t v = !mine ? ~0ull : (cand == ~0ull ? ~0ull - (uint64_t)lane : cand);
+  int rank = 0;
+  for (int j = 0; j <= k1; ++j) rank += readlane(v, j) < v ? 1 : 0;
   const int dst = (mine ? rank : lane) << 2;
-  const uint64_t v = mine ? cand : ~0ull;
   const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_permute(dst, (int)(uint32_t)v);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_permute(dst, (int)(uint32_t)(v >> 32));
   key = ((uint64_t)hi << 32) | lo;
   thr = readlane(key, k1);
+}
+
+// The k-th distance of a list as a float bound for a prefilter: +inf while the list is not
+// full (its k-th key is empty), else the d^2 of the k-th key.  A candidate can enter the
+// list only if its d^2 <= this bound.
+__device__ __forceinline__ float thr_float(uint64_t thr) {
+  const uint32_t hi = (uint32_t)(thr >> 32);
+  return hi == 0xFFFFFFFFu ? INFINITY : __uint_as_float(hi);
 }
 
 // Seed a list for query t from the previous query's list: its neighbours shifted one step
@@ -171,7 +177,7 @@ __device__ __forceinline__ double list_weight64(const float* x, int t, int nb, i
   const double d1 = __hiloint2double(readlane(__double2hiint(d), 0), readlane(__double2loint(d), 0));
   double u = 0.0;
   if (in) u = d1 > 0.0 ? exp(-d / d1) : (d == 0.0 ? 1.0 : 0.0);
-  usum = wave_sum(u);
+  usum = lanes32_sum(u);   // k <= 21: the list lives in lanes 0..31
   return u;
 }
 
@@ -283,7 +289,7 @@ __global__ __launch_bounds__(kKnnThreads) void knn_table_kernel(const float* __r
     double usum;
     double u = list_weight64(x, t, lane < k ? lidx : -1, E, tau, k, usum);
     if (lane < k_max) {
-      const bool in = lane < k;
+      const bool in = lane < k && lidx >= 0;
       nbr_idx[(rowbase + t) * k_max + lane] = in ? lidx : -1;
       nbr_w[(rowbase + t) * k_max + lane] = in ? (float)(u / usum) : 0.0f;
       if (nbr_d2) nbr_d2[(rowbase + t) * k_max + lane] = in ? ldist : INFINITY;
@@ -355,9 +361,17 @@ __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, 
     const bool seeded = t > tb;
     if (seeded) seed_group<ELO, 0, NG, TAU1, EHI>(x, t, tau, chi, half, qbase, E_lo, E_hi, xq,
                                                   key, thr);
+    // prefilter bound per list: -1 for a list not active at t (nothing passes)
+    float tf[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const int E = ELO + g;
+      tf[g] = (E >= E_lo && E <= E_hi && t >= qbase + (E - 1) * tau) ? thr_float(thr[g]) : -1.0f;
+    }
     // the window of candidates around t first when some list starts empty (HALF mode:
     // candidates are in the other half, so the window clamps to its end), then every chunk
-    // in order
+    // in order.  Candidates that are never admissible start at d^2 = +inf; a list takes the
+    // exact path (full admissibility, 64-bit keys) only when some lane passes its bound.
     const bool win = !seeded || t - 1 < qbase + (E_hi - 1) * tau;
     const int wb = win ? window_base(t, clo, chi) : chi + 1;
     for (int pass = win ? -1 : 0, base = clo; base <= chi;
@@ -365,21 +379,22 @@ __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, 
       const int b = pass < 0 ? wb : base;
       const int s = b + lane;
       const bool inr = s <= chi && (pass < 0 || s < wb || s >= wb + kWave);
+      const bool okc = inr && (half || s != t);
       const int sc = s <= chi ? s : chi;
       float xs[EHI];
       lag_values<EHI, TAU1>(x, sc, tau, xs);
-      float acc = 0.0f;
+      float acc = okc ? 0.0f : INFINITY;
 #pragma unroll
       for (int e = 0; e < EHI; ++e) {
         const float df = xq[e] - xs[e];
         acc = acc + df * df;
         if (e + 1 >= ELO) {
-          const int E = e + 1;
-          if (E >= E_lo && E <= E_hi && t >= qbase + (E - 1) * tau) {
-            const bool adm = inr && sc >= (E - 1) * tau && (half || s != t);
-            const uint64_t cand = adm ? nkey(acc, s) : ~0ull;
-            const int g = (e + 1 - ELO) >= 0 ? (e + 1 - ELO) : 0;
-            offer_chunk(cand, key[g], thr[g], E);
+          const int g = (e + 1 - ELO) >= 0 ? (e + 1 - ELO) : 0;
+          if (ballot(acc <= tf[g]) != 0) {
+            const int E = e + 1;
+            const bool adm = okc && sc >= (E - 1) * tau;
+            offer_chunk(adm ? nkey(acc, s) : ~0ull, key[g], thr[g], E);
+            tf[g] = thr_float(thr[g]);
           }
         }
       }
@@ -393,7 +408,7 @@ __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, 
         double usum;
         double u = list_weight64(x, t, li, E, tau, E + 1, usum);
         double f = (lane <= E && li >= 0) ? (double)x[li + Tp] : 0.0;
-        double pred = wave_sum(u * f) / usum;
+        double pred = lanes32_sum(u * f) / usum;
         if (lane == g) {
           double o = obs, p = pred;
           m_o += o;

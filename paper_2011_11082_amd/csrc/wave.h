@@ -8,6 +8,7 @@ namespace ccm {
 constexpr int kWave = 64;
 constexpr int kEMax = 20;
 constexpr int kKMax = kEMax + 1;
+static_assert(kKMax <= 32, "a neighbour list must fit in lanes 0..31");
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
@@ -48,6 +49,29 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
   return v;
+}
+
+// DPP move of a double (both halves), every lane a valid source.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum of lanes 0..31 (lanes 32..63 are ignored), returned in every lane: pairs and quads by
+// quad_perm, then rotations by 4 and 8 inside each row of 16, then the two row sums.  No LDS
+// round trip, unlike a shuffle butterfly.
+__device__ __forceinline__ double lanes32_sum(double v) {
+  v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_f64<0x124>(v);   // row_ror:4
+  v += dpp_f64<0x128>(v);   // row_ror:8
+  const double r0 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0),
+                                     __builtin_amdgcn_readlane(__double2loint(v), 0));
+  const double r1 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 16),
+                                     __builtin_amdgcn_readlane(__double2loint(v), 16));
+  return r0 + r1;
 }
 
 // Pearson correlation from one-pass FP64 moments of n pairs (y, p).  A variance below the
