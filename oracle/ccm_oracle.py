@@ -35,7 +35,9 @@ design notes):
   * optE is scored by leave-one-out simplex at Tp = 1 (query = candidate set, self
     excluded); the paper's half split is kept as ``mode = HALF``; the smallest E reaching
     the largest non-NaN rho wins;
-  * the cross-map uses the library's own E and Tp = 0; row = library, column = target.
+  * the cross-map uses the library's own E and Tp = 0; row = library, column = target;
+    ``crossmap_rho_target_E`` is the paper's own form, where each target picks the
+    libraries' tables at the target's E.
 
 Parity pins for every function live in tests/test_oracle_pins.py.
 """
@@ -49,7 +51,7 @@ MODE_HALF = 1
 __all__ = [
     "MODE_LOO", "MODE_HALF", "embed", "point_sets", "sqdist_fp32", "select_knn",
     "weights_fp64", "weights_rows_fp64", "pearson", "knn_table", "knn", "simplex_rho", "simplex_optE",
-    "crossmap_rho", "ccm_block", "crossmap_rho_grad",
+    "crossmap_rho", "ccm_block", "crossmap_rho_target_E", "crossmap_rho_grad",
 ]
 
 
@@ -301,6 +303,28 @@ def ccm_block(ts, lib_ids, lib_E, tau: int, tgt0: int, n_tgt: int, k_max=None):
     k_max = int(max(lib_E)) + 1 if k_max is None else k_max
     idx, w, d2 = knn(ts, lib_ids, lib_E, tau, 0, k_max)
     return crossmap_rho(ts, idx, w, lib_E, tau, tgt0, n_tgt), idx, w, d2
+
+
+def crossmap_rho_target_E(ts, lib_ids, tgt_E, tau: int, tgt0: int, n_tgt: int, k_max: int = 21):
+    """Alg. 2 as the paper prints it: target j is cross-mapped with every library's table at
+    the target's own optimal E, E_j = tgt_E[j] (Sec. III-B, phase 2 of Alg. 1).  One table
+    per (library, E) is shared by all targets of that E.
+
+    rho[i, j] = Pearson(Y[Q_i(E_j), j], yhat_ij) with yhat_ij(t) = sum_k w[t,k] Y[n_k(t), j]
+    over library i's table at E_j (Tp = 0).  FP64 after selection.
+    """
+    ts = np.asarray(ts, dtype=np.float32)
+    tgt_E = np.asarray(tgt_E, dtype=np.int64)
+    if tgt_E.shape != (n_tgt,):
+        raise ValueError("tgt_E needs one E per target")
+    n_lib = len(lib_ids)
+    rho = np.full((n_lib, n_tgt), np.nan)
+    for E in sorted(set(tgt_E.tolist())):
+        cols = np.nonzero(tgt_E == E)[0]
+        idx, w, _ = knn(ts, lib_ids, [E] * n_lib, tau, 0, k_max)
+        Y = ts[:, tgt0 + cols]
+        rho[:, cols] = crossmap_rho(Y, idx, w, [E] * n_lib, tau, 0, len(cols))
+    return rho
 
 
 # ---------------------------------------------------------------------------

@@ -330,3 +330,73 @@ def test_gradient_invariants_and_finite_differences():
                 assert np.array_equal(ii, idx[i][Q, : E + 1])
             fd = (loss(ts64, xp) - loss(ts64, xm)) / (2 * h)
             assert abs(fd - g_lib[i, s]) < 1e-6 * max(1.0, abs(g_lib[i, s]))
+
+
+# --- the paper's per-target-E cross-map (Alg. 2 as printed) -------------------------------
+def _brute_rho_target_E(xs, lib_cols, tgt_cols, tgt_E):
+    """Pure-Python brute force on integer series: for target j, library i's points at E_j
+    (Tp = 0, self excluded), the E_j + 1 nearest by exact integer d^2 then time index,
+    weights exp(-d/d1) normalised (zero-distance rule when d1 = 0), two-pass Pearson."""
+    L = len(xs[0])
+    out = []
+    for i in lib_cols:
+        x = xs[i]
+        row = []
+        for j, E in zip(tgt_cols, tgt_E):
+            y = xs[j]
+            Q = list(range(E - 1, L))
+            obs, pred = [], []
+            for t in Q:
+                cand = sorted((sum((x[t - e] - x[s - e]) ** 2 for e in range(E)), s)
+                              for s in Q if s != t)[:E + 1]
+                d = [math.sqrt(c[0]) for c in cand]
+                if d[0] > 0:
+                    u = [math.exp(-dk / d[0]) for dk in d]
+                else:
+                    u = [1.0 if dk == 0 else 0.0 for dk in d]
+                pred.append(sum(uk * y[c[1]] for uk, c in zip(u, cand)) / sum(u))
+                obs.append(float(y[t]))
+            mo, mp = sum(obs) / len(obs), sum(pred) / len(pred)
+            so = sum((a - mo) ** 2 for a in obs)
+            sp = sum((b - mp) ** 2 for b in pred)
+            sop = sum((a - mo) * (b - mp) for a, b in zip(obs, pred))
+            row.append(sop / math.sqrt(so * sp) if so > 0 and sp > 0 else float("nan"))
+        out.append(row)
+    return np.array(out)
+
+
+def test_target_E_cross_map_matches_brute_force():
+    rng = np.random.default_rng(21)
+    L, N = 22, 6
+    xs = rng.integers(0, 9, size=(N, L)).tolist()
+    ts = np.array(xs, dtype=np.float32).T.copy()
+    lib = [0, 2, 5]
+    tgt_E = [3, 1, 2, 3, 4, 1]          # one E per target column 0..5
+    rho = O.crossmap_rho_target_E(ts, lib, tgt_E, 1, 0, N, k_max=5)
+    bf = _brute_rho_target_E(xs, lib, list(range(N)), tgt_E)
+    np.testing.assert_allclose(rho, bf, rtol=0, atol=1e-12)
+
+
+def test_target_E_cross_map_periodic_and_columns():
+    rng = np.random.default_rng(12)
+    L, P = 150, 5
+    x = synth.periodic(P, L, rng)
+    tab = rng.standard_normal((3, P)).astype(np.float32)
+    ph = np.arange(L) % P
+    noise = rng.standard_normal(L).astype(np.float32)
+    # library 0 is P-periodic; targets 1..3 are functions of its phase, 4 is noise
+    ts = np.stack([x, tab[0][ph], tab[1][ph], tab[2][ph], noise], axis=1)
+    tgt_E = [2, 4, 1, 3, 2]
+    rho = O.crossmap_rho_target_E(ts, [0], tgt_E, 1, 0, 5, k_max=6)
+    np.testing.assert_allclose(rho[0, :4], 1.0, atol=1e-12)
+    assert rho[0, 4] < 0.9
+    # targets permuted together with their E permute the columns; a constant E reduces to
+    # the library-E form at that E
+    perm = [4, 2, 0, 3, 1]
+    ts_p = np.concatenate([ts[:, :1], ts[:, perm]], axis=1)     # library stays column 0
+    rho_p = O.crossmap_rho_target_E(ts_p, [0], [tgt_E[c] for c in perm], 1, 1, 5, k_max=6)
+    np.testing.assert_array_equal(rho_p, rho[:, perm])
+    for E in (1, 3):
+        r_const = O.crossmap_rho_target_E(ts, [0, 4], [E] * 5, 1, 0, 5, k_max=6)
+        r_lib, _, _, _ = O.ccm_block(ts, [0, 4], [E, E], 1, 0, 5, k_max=6)
+        np.testing.assert_array_equal(r_const, r_lib)
