@@ -130,6 +130,8 @@ def main():
     ap.add_argument("--n-lib", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-target-E", action="store_true",
+                    help="skip the per-target-E form (optE of every series + all-E tables)")
     ap.add_argument("--profile-steps", action="store_true",
                     help="no timing extras (for runs under rocprofv3)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -276,6 +278,36 @@ def main():
             "max_abs_drho_vs_fp32": float(d.max()) if d.numel() else None,
         }
         log(f"bf16 crossmap {t_bf:.2f} ms")
+
+    # The paper's per-target-E form (not part of the step; reported beside it): optE of every
+    # series (phase 1 at full N), each library's table at every E, then each target read
+    # through the tables at its own E.
+    if not args.no_target_E and not args.profile_steps:
+        all_ids = torch.arange(N, dtype=torch.int32, device=dev)
+        tE = {}
+        for rep in range(2):   # one warm-up, one timed
+            ea = ev(); ea.record()
+            optE_all, _ = ccm.simplex_optE(ts, all_ids, 1, wl.E_max, 1, 1, ccm.MODE_LOO)
+            eb = ev(); eb.record()
+            tidx, tw, _ = ccm.knn_all_E(ts, lib_ids, 1, wl.E_max, 1, 21)
+            ec = ev(); ec.record()
+            rho_t = ccm.crossmap_rho_target_E(ts, tidx, tw, n_lib, optE_all[wl.tgt0: wl.tgt0 + n_tgt],
+                                              E_lo=1, tgt0=wl.tgt0, n_tgt=n_tgt)
+            ed = ev(); ed.record()
+            torch.cuda.synchronize()
+            tE = {"optE_all_series_ms": round(ea.elapsed_time(eb), 2),
+                  "tables_all_E_ms": round(eb.elapsed_time(ec), 3),
+                  "crossmap_ms": round(ec.elapsed_time(ed), 3)}
+            del tidx, tw, rho_t
+        tE["n_series"] = N
+        tE["n_tables"] = n_lib * wl.E_max
+        tE["crossmap_rate"] = round(cross / (tE["crossmap_ms"] * 1e-3), 1)
+        tE["optE_hist_all_series"] = torch.bincount(optE_all.long(), minlength=21)[1:].tolist()
+        res["per_target_E"] = tE
+        log(f"per-target-E: optE of {N} series {tE['optE_all_series_ms']:.0f} ms, "
+            f"{tE['n_tables']} tables {tE['tables_all_E_ms']:.1f} ms, "
+            f"cross-map {tE['crossmap_ms']:.1f} ms")
+        del optE_all
 
     if not args.no_cpu_baseline and not args.profile_steps:
         log("timing the CPU oracle on a bounded sample")

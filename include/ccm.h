@@ -66,6 +66,7 @@ typedef int32_t ccm_status;
 #define CCM_OP_CROSSMAP_FP32 3
 #define CCM_OP_CROSSMAP_BF16 4
 #define CCM_OP_CROSSMAP_BACKWARD 5
+#define CCM_OP_CROSSMAP_TARGET_E 6   /* n_lib argument = number of (E, library) tables */
 
 /*
  * ccm_embed -- delay embedding (Sec. II-B; the explicit blocks of Alg. 4).
@@ -144,6 +145,31 @@ ccm_status ccm_crossmap_rho(const float* ts, int64_t ld, int32_t L, const int32_
                             int32_t k_max, int32_t tau, int32_t tgt0, int32_t n_tgt,
                             int32_t precision, float* rho, double* moments, void* ws,
                             size_t ws_bytes, void* stream);
+
+/*
+ * ccm_crossmap_rho_target_E -- the paper's own form of Alg. 2 (Sec. III-B): target j is
+ * cross-mapped with every library's table at the TARGET's E, E_j = tgt_E[j] (its optimal E
+ * from phase 1), so one table per (library, E) is shared by all targets of that E.
+ *   nbr_idx, nbr_w [n_E][n_lib][L][k_max]  tables from ccm_knn (Tp = 0), E-major: table
+ *                    e * n_lib + i is library i at E = E_lo + e (E_lo + n_E - 1 < k_max).
+ *   tgt_E [n_tgt]    E of each target (device); a target whose E is outside
+ *                    [E_lo, E_lo + n_E) gets rho = NaN in every row.
+ *   targets: series tgt0 .. tgt0 + n_tgt - 1 of ts.
+ *   rho[i][j] = Pearson over t = (E_j-1) tau .. L-1 of (ts[t * ld + tgt0 + j], yhat_ij(t)),
+ *   yhat_ij(t) = sum_k w[t,k] * ts[n_k(t) * ld + tgt0 + j] over library i's table at E_j;
+ *   FP32 products and sums per prediction, FP64 moments; NaN where a variance vanishes.
+ *   rho [n_lib][n_tgt], moments [n_lib][n_tgt][3] (nullable) as in ccm_crossmap_rho.
+ *   Targets are grouped by E on the device (no host synchronisation).
+ * Errors: EINVAL (nulls, sizes), ERANGE (E_lo, n_E, k_max, L), ENOTSUP (L > 2475),
+ * EWORKSPACE.  Workspace: ccm_workspace_size(CCM_OP_CROSSMAP_TARGET_E, L, n_E * n_lib,
+ * n_tgt, k_max).
+ */
+ccm_status ccm_crossmap_rho_target_E(const float* ts, int64_t ld, int32_t L,
+                                     const int32_t* nbr_idx, const float* nbr_w, int32_t n_lib,
+                                     int32_t E_lo, int32_t n_E, int32_t k_max, int32_t tau,
+                                     const int32_t* tgt_E, int32_t tgt0, int32_t n_tgt,
+                                     float* rho, double* moments, void* ws, size_t ws_bytes,
+                                     void* stream);
 
 /*
  * ccm_crossmap_rho_backward -- adjoint of loss = sum_p grad_rho[p] * rho[pair_lib[p]][pair_tgt[p]]

@@ -25,11 +25,12 @@ E_MAX = 20
 K_MAX = 21
 MODE_LOO, MODE_HALF = 0, 1
 PRECISION_FP32, PRECISION_BF16 = 0, 1
-OP_EMBED, OP_KNN, OP_SIMPLEX, OP_CROSSMAP_FP32, OP_CROSSMAP_BF16, OP_CROSSMAP_BACKWARD = range(6)
+(OP_EMBED, OP_KNN, OP_SIMPLEX, OP_CROSSMAP_FP32, OP_CROSSMAP_BF16, OP_CROSSMAP_BACKWARD,
+ OP_CROSSMAP_TARGET_E) = range(7)
 
 EXPORTED = (
     "ccm_embed", "ccm_knn", "ccm_simplex_optE", "ccm_crossmap_rho", "ccm_crossmap_rho_backward",
-    "ccm_workspace_size", "ccm_status_string", "ccm_last_error", "ccm_version",
+    "ccm_crossmap_rho_target_E", "ccm_workspace_size", "ccm_status_string", "ccm_last_error", "ccm_version",
 )
 
 
@@ -66,6 +67,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
                              _P, _P, _SZ, _P],
         "ccm_crossmap_rho_backward": [_P, _I64, _I32, _P, _P, _P, _P, _I32, _I32, _I32, _P, _P,
                                       _P, _I32, _P, _P, _P, _SZ, _P],
+        "ccm_crossmap_rho_target_E": [_P, _I64, _I32, _P, _P, _I32, _I32, _I32, _I32, _I32, _P,
+                                      _I32, _I32, _P, _P, _P, _SZ, _P],
         "ccm_workspace_size": [_I32, _I32, _I32, _I32, _I32, ctypes.POINTER(_SZ)],
         "ccm_status_string": [_I32],
         "ccm_last_error": [],
@@ -205,6 +208,51 @@ def crossmap_rho(ts: torch.Tensor, nbr_idx: torch.Tensor, nbr_w: torch.Tensor, l
     _check(lib.ccm_crossmap_rho(_ptr(ts), ld, L, _ptr(nbr_idx), _ptr(nbr_w), _ptr(lib_E), n_lib,
                                 k_max, tau, tgt0, n_tgt, precision, _ptr(rho), _ptr(mom), _ptr(ws),
                                 nbytes, _stream()))
+    return (rho, mom) if want_moments else rho
+
+
+def knn_all_E(ts: torch.Tensor, lib_ids, E_lo: int = 1, n_E: int = E_MAX, tau: int = 1,
+              k_max: int = K_MAX, want_d2: bool = False):
+    """Tables of every library at every E in E_lo .. E_lo + n_E - 1 (Tp = 0), E-major:
+    [n_E * n_lib][L][k_max], table e * n_lib + i = library i at E_lo + e.  One ccm_knn call
+    over the (E, library) pairs."""
+    ts, _, _ = _panel(ts)
+    ids = _i32(lib_ids, ts.device)
+    pair_ids = ids.repeat(n_E)
+    pair_E = torch.arange(E_lo, E_lo + n_E, dtype=torch.int32,
+                          device=ts.device).repeat_interleave(ids.numel())
+    return knn(ts, pair_ids, pair_E, tau, 0, k_max, want_d2=want_d2)
+
+
+def crossmap_rho_target_E(ts: torch.Tensor, nbr_idx: torch.Tensor, nbr_w: torch.Tensor,
+                          n_lib: int, tgt_E, E_lo: int = 1, tau: int = 1, tgt0: int = 0,
+                          n_tgt: Optional[int] = None, want_moments: bool = False,
+                          ws: Optional[torch.Tensor] = None):
+    """The paper's per-target-E cross-map: rho [n_lib][n_tgt], target j read through every
+    library's table at E = tgt_E[j] (tables from knn_all_E)."""
+    lib = load_library()
+    ts, ld, L = _panel(ts)
+    _dev(nbr_idx, "nbr_idx", torch.int32)
+    _dev(nbr_w, "nbr_w", torch.float32)
+    if not (nbr_idx.is_contiguous() and nbr_w.is_contiguous()):
+        raise ValueError("tables must be contiguous")
+    n_tab, L2, k_max = nbr_idx.shape
+    if L2 != L or nbr_w.shape != nbr_idx.shape or n_lib <= 0 or n_tab % n_lib:
+        raise ValueError("table shape does not match the panel or n_lib")
+    n_E = n_tab // n_lib
+    if n_tgt is None:
+        n_tgt = int(ts.shape[1]) - tgt0
+    tgt_E = _i32(tgt_E, ts.device)
+    if tgt_E.numel() != n_tgt:
+        raise ValueError("tgt_E needs one E per target")
+    rho = torch.empty((n_lib, n_tgt), dtype=torch.float32, device=ts.device)
+    mom = (torch.empty((n_lib, n_tgt, 3), dtype=torch.float64, device=ts.device)
+           if want_moments else None)
+    ws, need = _workspace(OP_CROSSMAP_TARGET_E, L, n_tab, n_tgt, k_max, ts.device, ws)
+    nbytes = ws.numel() if ws is not None else 0
+    _check(lib.ccm_crossmap_rho_target_E(_ptr(ts), ld, L, _ptr(nbr_idx), _ptr(nbr_w), n_lib,
+                                         E_lo, n_E, k_max, tau, _ptr(tgt_E), tgt0, n_tgt,
+                                         _ptr(rho), _ptr(mom), _ptr(ws), nbytes, _stream()))
     return (rho, mom) if want_moments else rho
 
 

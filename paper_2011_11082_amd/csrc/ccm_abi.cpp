@@ -25,6 +25,12 @@ hipError_t ccm_launch_crossmap_fp32(const float* ts, int64_t ld, int L, int tau,
                                     const int* lib_E, int n_lib, int k_max, float* rho,
                                     double* moments, uint32_t* poff, float* pw, int* lib_k,
                                     int* order, hipStream_t stream);
+int ccm_target_E_max_tiles(int n_tgt);
+hipError_t ccm_launch_crossmap_fp32_target_E(
+    const float* ts, int64_t ld, int L, int tau, int tgt0, int n_tgt, const int* nbr_idx,
+    const float* nbr_w, int n_lib, int E_lo, int n_E, int k_max, const int* tgt_E, float* rho,
+    double* moments, uint32_t* poff, float* pw, int* lib_k, int* table_E, int* perm, int* tiles,
+    int* ntiles, hipStream_t stream);
 size_t ccm_bf16_lds_bytes();
 hipError_t ccm_launch_crossmap_bf16(const float* ts, int64_t ld, int L, int tau, int tgt0, int n_tgt,
                                     const int* nbr_idx, const float* nbr_w, const int* lib_E,
@@ -72,6 +78,24 @@ CrossmapWs crossmap_ws(int L, int n_lib, int k_max) {
   w.off_libk = align_up(w.off_pw + ent * 4);
   w.off_order = align_up(w.off_libk + (size_t)n_lib * 4);
   w.total = align_up(w.off_order + (size_t)n_lib * 4);
+  return w;
+}
+
+// Workspace of the per-target-E cross-map: the FP32 workspace over n_tab = n_E * n_lib
+// tables, their E, the targets sorted by E, the tile list and its length.
+struct TargetEWs {
+  CrossmapWs tab;
+  size_t off_tabE, off_perm, off_tiles, off_ntiles, total;
+};
+
+TargetEWs target_E_ws(int L, int n_tab, int n_tgt, int k_max) {
+  TargetEWs w;
+  w.tab = crossmap_ws(L, n_tab, k_max);
+  w.off_tabE = w.tab.total;
+  w.off_perm = align_up(w.off_tabE + (size_t)n_tab * 4);
+  w.off_tiles = align_up(w.off_perm + (size_t)n_tgt * 4);
+  w.off_ntiles = align_up(w.off_tiles + (size_t)ccm_target_E_max_tiles(n_tgt) * 3 * 4);
+  w.total = align_up(w.off_ntiles + 4);
   return w;
 }
 
@@ -141,6 +165,9 @@ ccm_status ccm_workspace_size(int32_t op, int32_t L, int32_t n_lib, int32_t n_tg
       return CCM_OK;
     case CCM_OP_CROSSMAP_BF16:
       *bytes = bf16_ws(L, n_lib, n_tgt).total;
+      return CCM_OK;
+    case CCM_OP_CROSSMAP_TARGET_E:  // n_lib = number of (E, library) tables
+      *bytes = target_E_ws(L, n_lib, n_tgt, k_max).total;
       return CCM_OK;
     case CCM_OP_CROSSMAP_BACKWARD:  // n_tgt = number of pairs
       *bytes = ccm_backward_ws_bytes(L, n_tgt, k_max);
@@ -221,7 +248,7 @@ ccm_status ccm_crossmap_rho(const float* ts, int64_t ld, int32_t L, const int32_
   if (k_max < 2 || k_max > CCM_K_MAX) return fail(CCM_EINVAL, fn, "k_max outside [2, CCM_K_MAX]");
   if (L < 4) return fail(CCM_ERANGE, fn, "L < 4");
   if (precision == CCM_PRECISION_FP32) {
-    if (ccm_gather_lds_bytes(L) > 160 * 1024)
+    if (ccm_gather_lds_bytes(L) + 16 * sizeof(int) > 160 * 1024)
       return fail(CCM_ENOTSUP, fn, "L too large for the 16-target LDS tile (max 2475)");
     CrossmapWs w = crossmap_ws(L, n_lib, k_max);
     if (n_lib == 0 || n_tgt == 0) return CCM_OK;
@@ -246,6 +273,39 @@ ccm_status ccm_crossmap_rho(const float* ts, int64_t ld, int32_t L, const int32_
                                      (hipStream_t)stream));
   }
   return fail(CCM_EINVAL, fn, "unknown precision");
+}
+
+ccm_status ccm_crossmap_rho_target_E(const float* ts, int64_t ld, int32_t L,
+                                     const int32_t* nbr_idx, const float* nbr_w, int32_t n_lib,
+                                     int32_t E_lo, int32_t n_E, int32_t k_max, int32_t tau,
+                                     const int32_t* tgt_E, int32_t tgt0, int32_t n_tgt,
+                                     float* rho, double* moments, void* ws, size_t ws_bytes,
+                                     void* stream) {
+  const char* fn = "ccm_crossmap_rho_target_E";
+  ccm_status st = CCM_OK;
+  if (!check_series(fn, &st, ts, ld, L, tau)) return st;
+  if (n_lib < 0 || n_tgt < 0 || tgt0 < 0) return fail(CCM_EINVAL, fn, "negative size or offset");
+  if ((int64_t)tgt0 + n_tgt > ld) return fail(CCM_EINVAL, fn, "targets exceed the panel width ld");
+  if (k_max < 2 || k_max > CCM_K_MAX) return fail(CCM_EINVAL, fn, "k_max outside [2, CCM_K_MAX]");
+  if (E_lo < 1 || n_E < 1 || E_lo + n_E - 1 > CCM_E_MAX)
+    return fail(CCM_ERANGE, fn, "E_lo .. E_lo + n_E - 1 outside [1, CCM_E_MAX]");
+  if (E_lo + n_E > k_max) return fail(CCM_ERANGE, fn, "k_max < largest E + 1");
+  if ((int64_t)n_E * n_lib > INT32_MAX / 2) return fail(CCM_EINVAL, fn, "too many tables");
+  if (n_lib > 0 && n_tgt > 0 && (!nbr_idx || !nbr_w || !tgt_E || !rho))
+    return fail(CCM_EINVAL, fn, "NULL array argument");
+  if (L < 4) return fail(CCM_ERANGE, fn, "L < 4");
+  if (ccm_gather_lds_bytes(L) + 16 * sizeof(int) > 160 * 1024)
+    return fail(CCM_ENOTSUP, fn, "L too large for the 16-target LDS tile (max 2475)");
+  const TargetEWs w = target_E_ws(L, n_E * n_lib, n_tgt, k_max);
+  if (n_lib == 0 || n_tgt == 0) return CCM_OK;
+  if (!ws || ws_bytes < w.total) return fail(CCM_EWORKSPACE, fn, "workspace too small");
+  char* base = (char*)ws;
+  return device_status(
+      fn, ccm_launch_crossmap_fp32_target_E(
+              ts, ld, L, tau, tgt0, n_tgt, nbr_idx, nbr_w, n_lib, E_lo, n_E, k_max, tgt_E, rho,
+              moments, (uint32_t*)(base + w.tab.off_poff), (float*)(base + w.tab.off_pw),
+              (int*)(base + w.tab.off_libk), (int*)(base + w.off_tabE), (int*)(base + w.off_perm),
+              (int*)(base + w.off_tiles), (int*)(base + w.off_ntiles), (hipStream_t)stream));
 }
 
 ccm_status ccm_crossmap_rho_backward(const float* ts, int64_t ld, int32_t L, const float* lib_ts,

@@ -136,6 +136,77 @@ __global__ __launch_bounds__(256) void prep_tables_kernel(
 }
 
 // ---------------------------------------------------------------------------------------
+// Targets grouped by E (the paper's Alg. 2 as printed: each target is cross-mapped with the
+// libraries' tables at the target's own E).  One workgroup: a stable counting sort of the
+// targets into buckets b = E - E_lo (bucket n_E: E without a table), then the tile list
+// (bucket, first position, column count) with at most 16 columns per tile.
+// ---------------------------------------------------------------------------------------
+constexpr int kBucketThreads = 512;
+constexpr int kBuckets = kEMax + 1;
+
+__global__ __launch_bounds__(kBucketThreads) void bucket_targets_kernel(
+    const int* __restrict__ tgt_E, int n_tgt, int E_lo, int n_E, int* __restrict__ perm,
+    int* __restrict__ tiles, int* __restrict__ ntiles) {
+  __shared__ int cnt[kBuckets][kBucketThreads];
+  __shared__ int bstart[kBuckets + 1];
+  __shared__ int tstart[kBuckets + 1];
+  const int tid = threadIdx.x;
+  const int chunk = (n_tgt + kBucketThreads - 1) / kBucketThreads;
+  const int lo = min(tid * chunk, n_tgt);
+  const int hi = min(lo + chunk, n_tgt);
+  for (int b = 0; b < kBuckets; ++b) cnt[b][tid] = 0;
+  for (int j = lo; j < hi; ++j) {
+    const int e = tgt_E[j] - E_lo;
+    cnt[(e >= 0 && e < n_E) ? e : n_E][tid]++;
+  }
+  __syncthreads();
+  if (tid < kBuckets) {   // exclusive scan of bucket tid over threads
+    int acc = 0;
+    for (int th = 0; th < kBucketThreads; ++th) {
+      const int c = cnt[tid][th];
+      cnt[tid][th] = acc;
+      acc += c;
+    }
+    bstart[tid] = acc;    // bucket size for now
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int pos = 0, tl = 0;
+    for (int b = 0; b < kBuckets; ++b) {
+      const int c = bstart[b];
+      bstart[b] = pos;
+      tstart[b] = tl;
+      pos += c;
+      tl += (c + kTJ - 1) / kTJ;
+    }
+    bstart[kBuckets] = pos;
+    tstart[kBuckets] = tl;
+    *ntiles = tl;
+  }
+  __syncthreads();
+  for (int j = lo; j < hi; ++j) {
+    const int e = tgt_E[j] - E_lo;
+    const int b = (e >= 0 && e < n_E) ? e : n_E;
+    perm[bstart[b] + cnt[b][tid]++] = j;
+  }
+  for (int T = tid; T < tstart[kBuckets]; T += kBucketThreads) {
+    int b = 0;
+    while (tstart[b + 1] <= T) ++b;
+    const int m = T - tstart[b];
+    const int size = bstart[b + 1] - bstart[b];
+    tiles[3 * T] = b;
+    tiles[3 * T + 1] = bstart[b] + m * kTJ;
+    tiles[3 * T + 2] = min(kTJ, size - m * kTJ);
+  }
+}
+
+// E of table v = e * n_lib + i (tables ordered E-major): E_lo + e.
+__global__ void fill_table_E_kernel(int* __restrict__ table_E, int n_lib, int E_lo, int n_tab) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n_tab) table_E[v] = E_lo + v / n_lib;
+}
+
+// ---------------------------------------------------------------------------------------
 // The gather.  grid = (target tiles, library splits), block = 1024 threads.
 // LDS: tile [L][16] floats, then column sums sy[E][16], syy[E][16] (FP64, E = 1..20).
 // ---------------------------------------------------------------------------------------
@@ -268,23 +339,44 @@ __device__ __forceinline__ void gather_library(const char* smem, const uint32_t*
   }
 }
 
+// Two ways to form a workgroup's 16 target columns and its tables:
+//   * tiles == NULL: columns j0..j0+15 (j0 = 16 * blockIdx.x), every library with its own
+//     table (library row i = order[li], table i);
+//   * tiles != NULL (targets grouped by E): tile entry blockIdx.x = (bucket b, first
+//     position in perm, column count); column c is target perm[first + c], and library row
+//     i uses table b * n_lib + i, the library's table at the bucket's E.  Bucket n_E holds
+//     targets whose E has no table: their rho is NaN.  Entries past *ntiles exit at once.
 __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
     const float* __restrict__ ts, int64_t ld, int L, int tau, int tgt0, int n_tgt,
     const uint32_t* __restrict__ poff, const float* __restrict__ pw, const int* __restrict__ order,
     const int* __restrict__ lib_k, int n_lib, int nblk, int KSM, float* __restrict__ rho,
-    double* __restrict__ moments) {
+    double* __restrict__ moments, const int* __restrict__ tiles, const int* __restrict__ ntiles,
+    const int* __restrict__ perm, int n_E) {
   extern __shared__ __align__(16) char smem[];
   float* tile = (float*)smem;
   double* sy = (double*)(smem + (size_t)L * kRowBytes);      // [kEMax + 1][16]
   double* syy = sy + (kEMax + 1) * kTJ;
+  __shared__ int colmap[kTJ];   // target column of each tile column, -1 if none
 
-  const int j0 = blockIdx.x * kTJ;
-  // load the tile (rows 0..L-1, 16 columns; columns past n_tgt read as 0)
+  int vbase = 0;
+  bool no_table = false;
+  if (tiles) {
+    if ((int)blockIdx.x >= *ntiles) return;   // whole workgroup: past the tile list
+    const int* te = tiles + 3 * blockIdx.x;
+    const int b = te[0], first = te[1], cnt = te[2];
+    if (threadIdx.x < kTJ) colmap[threadIdx.x] = (int)threadIdx.x < cnt ? perm[first + threadIdx.x] : -1;
+    vbase = b * n_lib;
+    no_table = b >= n_E;
+  } else if (threadIdx.x < kTJ) {
+    const int j = blockIdx.x * kTJ + threadIdx.x;
+    colmap[threadIdx.x] = j < n_tgt ? j : -1;
+  }
+  __syncthreads();
+  // load the tile (rows 0..L-1, 16 columns; missing columns read as 0)
   for (int g = threadIdx.x; g < L * kTJ; g += blockDim.x) {
     const int t = g >> 4;
-    const int c = g & 15;
-    const int j = j0 + c;
-    tile[g] = j < n_tgt ? ts[(int64_t)t * ld + tgt0 + j] : 0.0f;
+    const int j = colmap[g & 15];
+    tile[g] = j >= 0 ? ts[(int64_t)t * ld + tgt0 + j] : 0.0f;
   }
   __syncthreads();
   // FP64 sums of y and y^2 over t >= (E-1) tau, per E and column
@@ -312,13 +404,15 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
   const size_t libstride = (size_t)nblk * KSM * kWave;
 
   for (int li = blockIdx.y + splits * wave; li < n_lib; li += splits * nw) {
-    const int i = __builtin_amdgcn_readfirstlane(order[li]);
-    const int k = __builtin_amdgcn_readfirstlane(lib_k[i]);
+    const int i = __builtin_amdgcn_readfirstlane(order ? order[li] : li);
+    const int v = vbase + i;   // table of this library row
+    const int k = no_table ? 0 : __builtin_amdgcn_readfirstlane(lib_k[v]);
     if (k == 0) {
-      if (lane < kTJ && j0 + lane < n_tgt) {
-        rho[(size_t)i * n_tgt + j0 + lane] = __builtin_nanf("");
+      const int j = lane < kTJ ? colmap[lane] : -1;
+      if (j >= 0) {
+        rho[(size_t)i * n_tgt + j] = __builtin_nanf("");
         if (moments) {
-          double* mo = moments + ((size_t)i * n_tgt + j0 + lane) * 3;
+          double* mo = moments + ((size_t)i * n_tgt + j) * 3;
           mo[0] = mo[1] = mo[2] = __builtin_nan("");
         }
       }
@@ -326,8 +420,8 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
     }
     const int E = k - 1;
     const int lo = (E - 1) * tau;
-    const uint32_t* po = poff + (size_t)i * libstride;
-    const float* pq = pw + (size_t)i * libstride;
+    const uint32_t* po = poff + (size_t)v * libstride;
+    const float* pq = pw + (size_t)v * libstride;
     Moments m;
     m.sp = m.spp = m.syp = float4{0, 0, 0, 0};
 #pragma unroll
@@ -357,8 +451,8 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int col = 4 * l + c;
-        const int j = j0 + col;
-        if (j < n_tgt) {
+        const int j = colmap[col];
+        if (j >= 0) {
           const double r = pearson_from_moments(n, sy[E * kTJ + col], syy[E * kTJ + col],
                                                 m.dp[c], m.dpp[c], m.dyp[c]);
           rho[(size_t)i * n_tgt + j] = (float)r;
@@ -374,6 +468,32 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
   }
 }
 
+}  // namespace ccm
+
+namespace ccm {
+// The gather's LDS tile needs more than the default dynamic LDS limit: allow all of the
+// CU's 160 KB minus the kernel's static LDS.
+hipError_t gather_allow_lds() {
+  static bool done = false;
+  if (done) return hipSuccess;
+  hipFuncAttributes fa;
+  hipError_t e = hipFuncGetAttributes(&fa, (const void*)gather_fp32_kernel);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)gather_fp32_kernel,
+                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                          160 * 1024 - (int)fa.sharedSizeBytes);
+  if (e == hipSuccess) done = true;
+  return e;
+}
+
+// Library splits (grid.y): enough workgroups to fill the chip when there are few tiles, no
+// more than one library per wave.
+int gather_splits(int n_tiles, int n_lib) {
+  int splits = (1024 + n_tiles - 1) / n_tiles;
+  const int max_splits = (n_lib + kGatherThreads / kWave - 1) / (kGatherThreads / kWave);
+  if (splits > max_splits) splits = max_splits;
+  return splits < 1 ? 1 : splits;
+}
 }  // namespace ccm
 
 extern "C" hipError_t ccm_launch_order(const int* lib_k, int n_lib, int* order, hipStream_t stream) {
@@ -399,20 +519,45 @@ extern "C" hipError_t ccm_launch_crossmap_fp32(const float* ts, int64_t ld, int 
                      stream, nbr_idx, nbr_w, lib_E, n_lib, L, k_max, tau, nblk, KSM, poff, pw, lib_k);
   hipLaunchKernelGGL(ccm::order_kernel, dim3(1), dim3(256), 0, stream, lib_k, n_lib, order);
   const size_t lds = ccm_gather_lds_bytes(L);
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)ccm::gather_fp32_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  hipError_t e = ccm::gather_allow_lds();
+  if (e != hipSuccess) return e;
   const int n_tiles = (n_tgt + ccm::kTJ - 1) / ccm::kTJ;
-  int splits = (1024 + n_tiles - 1) / n_tiles;
-  const int max_splits = (n_lib + ccm::kGatherThreads / ccm::kWave - 1) / (ccm::kGatherThreads / ccm::kWave);
-  if (splits > max_splits) splits = max_splits;
-  if (splits < 1) splits = 1;
+  const int splits = ccm::gather_splits(n_tiles, n_lib);
   hipLaunchKernelGGL(ccm::gather_fp32_kernel, dim3(n_tiles, splits), dim3(ccm::kGatherThreads), lds,
                      stream, ts, ld, L, tau, tgt0, n_tgt, poff, pw, order, lib_k, n_lib, nblk, KSM,
-                     rho, moments);
+                     rho, moments, nullptr, nullptr, nullptr, 0);
+  return hipGetLastError();
+}
+
+// Maximum number of tile entries for n_tgt targets: every bucket may end in a partial tile.
+extern "C" int ccm_target_E_max_tiles(int n_tgt) {
+  return (n_tgt + ccm::kTJ - 1) / ccm::kTJ + ccm::kBuckets;
+}
+
+extern "C" hipError_t ccm_launch_crossmap_fp32_target_E(
+    const float* ts, int64_t ld, int L, int tau, int tgt0, int n_tgt, const int* nbr_idx,
+    const float* nbr_w, int n_lib, int E_lo, int n_E, int k_max, const int* tgt_E, float* rho,
+    double* moments, uint32_t* poff, float* pw, int* lib_k, int* table_E, int* perm, int* tiles,
+    int* ntiles, hipStream_t stream) {
+  if (n_lib == 0 || n_tgt == 0) return hipSuccess;
+  const int nblk = (L + 15) / 16;
+  const int KSM = (k_max + 3) / 4;
+  const int n_tab = n_E * n_lib;
+  hipLaunchKernelGGL(ccm::fill_table_E_kernel, dim3((n_tab + 255) / 256), dim3(256), 0, stream,
+                     table_E, n_lib, E_lo, n_tab);
+  const int64_t rows = (int64_t)n_tab * nblk * 16;
+  hipLaunchKernelGGL(ccm::prep_tables_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0,
+                     stream, nbr_idx, nbr_w, table_E, n_tab, L, k_max, tau, nblk, KSM, poff, pw,
+                     lib_k);
+  hipLaunchKernelGGL(ccm::bucket_targets_kernel, dim3(1), dim3(ccm::kBucketThreads), 0, stream,
+                     tgt_E, n_tgt, E_lo, n_E, perm, tiles, ntiles);
+  hipError_t e = ccm::gather_allow_lds();
+  if (e != hipSuccess) return e;
+  const int max_tiles = ccm_target_E_max_tiles(n_tgt);
+  const int splits = ccm::gather_splits(max_tiles, n_lib);
+  hipLaunchKernelGGL(ccm::gather_fp32_kernel, dim3(max_tiles, splits), dim3(ccm::kGatherThreads),
+                     ccm_gather_lds_bytes(L), stream, ts, ld, L, tau, tgt0, n_tgt, poff, pw,
+                     (const int*)nullptr, lib_k, n_lib, nblk, KSM, rho, moments, tiles, ntiles,
+                     perm, n_E);
   return hipGetLastError();
 }

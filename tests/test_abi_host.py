@@ -105,3 +105,30 @@ def test_backward_argument_errors():
                                          fake, 0, fake, fake, _null(), 0, _null()) == ccm.CCM_OK
     n = ccm.workspace_size(ccm.OP_CROSSMAP_BACKWARD, 1000, 2048, 256, 21)
     assert n >= 256 * 1000 * 21 * 4
+
+
+def test_target_E_argument_errors_and_workspace():
+    lib = ccm.load_library()
+    fake = ctypes.c_void_p(0x1000)
+    f = lib.ccm_crossmap_rho_target_E
+    # args: ts, ld, L, idx, w, n_lib, E_lo, n_E, k_max, tau, tgt_E, tgt0, n_tgt, rho, mom, ws,
+    #       ws_bytes, stream
+    assert f(fake, 64, 100, fake, fake, 4, 0, 5, 21, 1, fake, 0, 64, fake, _null(), fake, 1 << 30,
+             _null()) == ccm.CCM_ERANGE                      # E_lo < 1
+    assert f(fake, 64, 100, fake, fake, 4, 15, 8, 21, 1, fake, 0, 64, fake, _null(), fake, 1 << 30,
+             _null()) == ccm.CCM_ERANGE                      # largest E 22 > CCM_E_MAX
+    assert f(fake, 64, 100, fake, fake, 4, 1, 10, 8, 1, fake, 0, 64, fake, _null(), fake, 1 << 30,
+             _null()) == ccm.CCM_ERANGE                      # k_max < largest E + 1
+    assert f(fake, 64, 100, fake, fake, 4, 1, 5, 21, 1, _null(), 0, 64, fake, _null(), fake,
+             1 << 30, _null()) == ccm.CCM_EINVAL             # tgt_E NULL
+    assert f(fake, 64, 100, fake, fake, 4, 1, 5, 21, 1, fake, 8, 64, fake, _null(), fake, 1 << 30,
+             _null()) == ccm.CCM_EINVAL                      # targets past the panel
+    assert f(fake, 64, 100, fake, fake, 4, 1, 5, 21, 1, fake, 0, 64, fake, _null(), fake, 64,
+             _null()) == ccm.CCM_EWORKSPACE
+    assert f(fake, 64, 2476, fake, fake, 4, 1, 5, 21, 1, fake, 0, 64, fake, _null(), fake,
+             1 << 30, _null()) == ccm.CCM_ENOTSUP            # tile does not fit in LDS
+    assert b"2475" in lib.ccm_last_error()
+    # workspace grows with the number of (E, library) tables and covers the tile list
+    a = ccm.workspace_size(ccm.OP_CROSSMAP_TARGET_E, 1600, 20 * 512, 101729, 21)
+    b = ccm.workspace_size(ccm.OP_CROSSMAP_FP32, 1600, 20 * 512, 101729, 21)
+    assert a >= b + 101729 * 4 + ((101729 + 15) // 16 + 21) * 12
