@@ -15,11 +15,14 @@
 //     owns 64 rows of a 128-row chunk of its library against the 128 targets: a 64 x 128
 //     FP32 accumulator (2 x 4 tiles of v_mfma_f32_32x32x16_bf16).
 //   * K (the neighbour time s) advances in stages of 64: the workgroup stages Y^T[128][64]
-//     BF16 in LDS (double-buffered, loaded one stage ahead through registers) and each wave
+//     BF16 in LDS (double-buffered, loaded two stages ahead through registers) and each wave
 //     scatters the nonzeros of its 64 rows into its own zeroed A tile [64][64]; after its
 //     products it writes the same positions back to zero (the tile is private to the
-//     wave, so program order is the only ordering needed).  A stage whose A tile
-//     is empty for a wave skips that wave's products.
+//     wave, so program order is the only ordering needed).  Every stage runs its products
+//     unconditionally: a branch around them would make the compiler move all 128
+//     accumulators between AGPRs and VGPRs at every stage.
+//   * The stage loop is unrolled by two so the two B register sets alternate roles (each
+//     is stored to LDS, then reloaded two stages ahead) without register copies.
 //   * Table entries are pre-sorted per (library, 128-row chunk) by stage and packed into
 //     32 bits (row, column within stage, BF16 weight).
 #include <hip/hip_runtime.h>
@@ -194,7 +197,9 @@ __global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
       breg2[q] = (brow_ok && nst > 1) ? *(const uint4*)(ysrc + kStage + q * 8) : uint4{0, 0, 0, 0};
     }
     __syncthreads();  // staged entries visible to both waves of each library
-    for (int st = 0; st < nst; ++st) {
+    // one stage; R holds this stage's B rows and is reloaded with stage st + 2 once stored,
+    // so the two register sets alternate without copies
+    auto stage = [&](int st, uint4 (&R)[4]) {
       const int buf = st & 1;
       // scatter this wave's nonzeros of the stage (rows of its half only)
       int e0 = 0, e1 = 0;
@@ -210,33 +215,28 @@ __global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
       {
         uint16_t* dst = Bs + (size_t)buf * kBTN * kRS + br * kRS + bh * 32;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) *(uint4*)(dst + q * 8) = breg[q];
+        for (int q = 0; q < 4; ++q) *(uint4*)(dst + q * 8) = R[q];
       }
       __syncthreads();  // B stage `buf` complete; the other buffer is free
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        breg[q] = breg2[q];
-        breg2[q] = (brow_ok && st + 2 < nst)
-                       ? *(const uint4*)(ysrc + (size_t)(st + 2) * kStage + q * 8)
-                       : uint4{0, 0, 0, 0};
-      }
-      if (e1 > e0) {
-        const uint16_t* Bb = Bs + (size_t)buf * kBTN * kRS;
+      for (int q = 0; q < 4; ++q)
+        R[q] = (brow_ok && st + 2 < nst) ? *(const uint4*)(ysrc + (size_t)(st + 2) * kStage + q * 8)
+                                         : uint4{0, 0, 0, 0};
+      const uint16_t* Bb = Bs + (size_t)buf * kBTN * kRS;
 #pragma unroll
-        for (int kk = 0; kk < kStage / 16; ++kk) {
-          bf16x8 af[2], bfr[4];
+      for (int kk = 0; kk < kStage / 16; ++kk) {
+        bf16x8 af[2], bfr[4];
 #pragma unroll
-          for (int a = 0; a < 2; ++a)
-            af[a] = *(const bf16x8*)(Aw + (32 * a + (lane & 31)) * kRS + 16 * kk + 8 * (lane >> 5));
+        for (int a = 0; a < 2; ++a)
+          af[a] = *(const bf16x8*)(Aw + (32 * a + (lane & 31)) * kRS + 16 * kk + 8 * (lane >> 5));
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          bfr[b] = *(const bf16x8*)(Bb + (32 * b + (lane & 31)) * kRS + 16 * kk + 8 * (lane >> 5));
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
           for (int b = 0; b < 4; ++b)
-            bfr[b] = *(const bf16x8*)(Bb + (32 * b + (lane & 31)) * kRS + 16 * kk + 8 * (lane >> 5));
-#pragma unroll
-          for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-              acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
-        }
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
       }
       // clear this wave's nonzeros again (after its own reads, in program order)
       for (int e = e0 + lane; e < e1; e += kWave) {
@@ -244,7 +244,13 @@ __global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
         const int row = v & 127;
         if ((row >> 6) == half) Aw[(row & 63) * kRS + ((v >> 7) & 63)] = 0;
       }
+    };
+    int st = 0;
+    for (; st + 1 < nst; st += 2) {
+      stage(st, breg);
+      stage(st + 1, breg2);
     }
+    if (st < nst) stage(st, breg);
     // epilogue: moments of this chunk's rows
     if (mine) {
 #pragma unroll
