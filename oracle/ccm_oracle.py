@@ -18,6 +18,8 @@ Dynamics at Single Neuron Resolution", IEEE eScience 2020):
   * corrcoef (Pearson rho)     -- Sec. III-A, Alg. 1 / Alg. 2
   * simplex projection / optE  -- Sec. II-B and Sec. III-A, Alg. 1 phase 1 (argmax over E)
   * table reuse across targets -- Sec. III-B, Alg. 2 (one table per library, every target)
+  * convergence test           -- Sec. III-A (skill against library size over random
+                                  library subsamples; the paper skips it)
 
 Readings where the paper is silent or garbled (each is listed with its reason in the
 design notes):
@@ -51,7 +53,7 @@ MODE_HALF = 1
 __all__ = [
     "MODE_LOO", "MODE_HALF", "embed", "point_sets", "sqdist_fp32", "select_knn",
     "weights_fp64", "weights_rows_fp64", "pearson", "knn_table", "knn", "simplex_rho", "simplex_optE",
-    "crossmap_rho", "ccm_block", "crossmap_rho_target_E", "crossmap_rho_grad",
+    "crossmap_rho", "ccm_block", "crossmap_rho_target_E", "ccm_convergence", "crossmap_rho_grad",
 ]
 
 
@@ -196,12 +198,18 @@ def pearson(a, b) -> float:
     return float(np.sum(da * db) / np.sqrt(saa * sbb))
 
 
-def knn_table(x, E: int, tau: int, Tp: int, mode: int = MODE_LOO):
+def knn_table(x, E: int, tau: int, Tp: int, mode: int = MODE_LOO, cand=None):
     """Neighbour table of one series at one E: (Q, idx [|Q|][E+1], w [|Q|][E+1] FP64,
-    d2 [|Q|][E+1] FP32).  k = E + 1 (Sec. III-A: the E+1 nearest points)."""
+    d2 [|Q|][E+1] FP32).  k = E + 1 (Sec. III-A: the E+1 nearest points).
+
+    cand (optional bool [L]): only time indices marked True may be neighbours (a library
+    subsample of the CCM convergence test); every point is still a query.
+    """
     x32 = np.asarray(x, dtype=np.float32)
     L = x32.shape[0]
     Q, C, excl = point_sets(L, E, tau, Tp, mode)
+    if cand is not None:
+        C = C[np.asarray(cand, dtype=bool)[C]]
     k = E + 1
     D2 = sqdist_fp32(x32, Q, C, E, tau)
     idx, d2 = select_knn(D2, Q, C, k, excl)
@@ -209,11 +217,12 @@ def knn_table(x, E: int, tau: int, Tp: int, mode: int = MODE_LOO):
     return Q, idx, w, d2
 
 
-def knn(ts, lib_ids, lib_E, tau: int, Tp: int, k_max: int):
+def knn(ts, lib_ids, lib_E, tau: int, Tp: int, k_max: int, cand_masks=None):
     """Tables of many libraries in the library's layout [n_lib][L][k_max].
 
     Row t holds the table row of query t; rows outside Q and slots beyond E_i + 1 are
-    padding (idx = -1, w = 0, d2 = +inf).
+    padding (idx = -1, w = 0, d2 = +inf).  cand_masks (optional bool [n_lib][L]) restricts
+    each library's neighbours to its marked time indices.
     """
     ts = np.asarray(ts, dtype=np.float32)
     L = ts.shape[0]
@@ -225,7 +234,8 @@ def knn(ts, lib_ids, lib_E, tau: int, Tp: int, k_max: int):
         E = int(E)
         if E + 1 > k_max:
             raise ValueError("E + 1 > k_max")
-        Q, idx, w, d2 = knn_table(ts[:, sid], E, tau, Tp)
+        Q, idx, w, d2 = knn_table(ts[:, sid], E, tau, Tp,
+                                  cand=None if cand_masks is None else cand_masks[i])
         idx_out[i, Q, : E + 1] = idx
         w_out[i, Q, : E + 1] = w
         d2_out[i, Q, : E + 1] = d2
@@ -324,6 +334,27 @@ def crossmap_rho_target_E(ts, lib_ids, tgt_E, tau: int, tgt0: int, n_tgt: int, k
         idx, w, _ = knn(ts, lib_ids, [E] * n_lib, tau, 0, k_max)
         Y = ts[:, tgt0 + cols]
         rho[:, cols] = crossmap_rho(Y, idx, w, [E] * n_lib, tau, 0, len(cols))
+    return rho
+
+
+def ccm_convergence(ts, lib_ids, lib_E, masks, tau: int, tgt0: int, n_tgt: int,
+                    k_max: int = 21):
+    """CCM convergence test (Sec. III-A recalls it as part of the original CCM definition --
+    predictions repeated over random library subsamples of growing size -- and leaves it
+    out of Alg. 1): for library i and each candidate mask r (a random library subsample),
+    library i's table at E_i with neighbours drawn only from the subsample (every point
+    is a query, self excluded), then the cross-map rho of each target.
+
+    masks: bool [n_lib][n_samp][L].  Returns rho [n_lib][n_samp][n_tgt].
+    """
+    masks = np.asarray(masks, dtype=bool)
+    n_lib, n_samp = masks.shape[0], masks.shape[1]
+    rho = np.full((n_lib, n_samp, n_tgt), np.nan)
+    for i in range(n_lib):
+        E = int(lib_E[i])
+        idx, w, _ = knn(ts, [lib_ids[i]] * n_samp, [E] * n_samp, tau, 0, k_max,
+                        cand_masks=masks[i])
+        rho[i] = crossmap_rho(ts, idx, w, [E] * n_samp, tau, tgt0, n_tgt)
     return rho
 
 

@@ -259,3 +259,40 @@ def periodic(P: int, L: int, rng: np.random.Generator) -> np.ndarray:
     """A series that repeats exactly with period P (x(t) = tab[t mod P])."""
     tab = rng.standard_normal(P).astype(np.float32)
     return tab[np.arange(L) % P]
+
+
+def library_samples(L: int, E: int, sizes, n_samples: int, seed: int, tau: int = 1) -> np.ndarray:
+    """Random library subsamples for the CCM convergence test: for each size m in `sizes`
+    and each of `n_samples` draws, a boolean mask over time indices [L] marking m points
+    drawn without replacement from the embedded points {(E-1) tau, ..., L-1}.
+
+    Draw order: sizes in the given order, samples in order, one `rng.choice` each, from
+    `default_rng([7, seed, E])`.  Returns bool [len(sizes) * n_samples][L].
+    """
+    rng = np.random.default_rng([7, seed, E])
+    lo = (E - 1) * tau
+    pts = np.arange(lo, L)
+    out = np.zeros((len(sizes) * n_samples, L), dtype=bool)
+    r = 0
+    for m in sizes:
+        if m > pts.size:
+            raise ValueError(f"library size {m} exceeds the {pts.size} embedded points")
+        for _ in range(n_samples):
+            out[r, rng.choice(pts, size=m, replace=False)] = True
+            r += 1
+    return out
+
+
+def two_species(T: int, seed: int, *, rx=3.8, ry=3.5, bxy=0.02, byx=0.1, burn=300) -> np.ndarray:
+    """Two coupled logistic maps (x drives y more strongly than y drives x):
+    x(t+1) = x(t) (rx - rx x(t) - bxy y(t)),  y(t+1) = y(t) (ry - ry y(t) - byx x(t)).
+    Draw order: x0, y0 ~ U(0.2, 0.8) from `default_rng([8, seed])`.  Returns float32 [T][2]
+    with columns (x, y)."""
+    rng = np.random.default_rng([8, seed])
+    x, y = rng.uniform(0.2, 0.8, size=2)
+    out = np.empty((T, 2), dtype=np.float64)
+    for t in range(burn + T):
+        if t >= burn:
+            out[t - burn] = (x, y)
+        x, y = x * (rx - rx * x - bxy * y), y * (ry - ry * y - byx * x)
+    return out.astype(np.float32)

@@ -400,3 +400,62 @@ def test_target_E_cross_map_periodic_and_columns():
         r_const = O.crossmap_rho_target_E(ts, [0, 4], [E] * 5, 1, 0, 5, k_max=6)
         r_lib, _, _, _ = O.ccm_block(ts, [0, 4], [E, E], 1, 0, 5, k_max=6)
         np.testing.assert_array_equal(r_const, r_lib)
+
+
+# --- the CCM convergence test: tables over random library subsamples ----------------------
+def _brute_knn_subset(xi, E, allowed, k):
+    """Pure-Python brute force: every point is a query; neighbours come only from the
+    allowed time indices (self excluded); exact integer d^2, ties to the lower index."""
+    L = len(xi)
+    out = {}
+    for t in range(E - 1, L):
+        cand = sorted((sum((xi[t - e] - xi[s - e]) ** 2 for e in range(E)), s)
+                      for s in allowed if s != t and s >= E - 1)
+        out[t] = [s for _, s in cand[:k]]
+    return out
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_subsampled_knn_matches_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    L = 60
+    xi = rng.integers(0, 5, size=L).tolist()
+    x = np.array(xi, dtype=np.float32)
+    for E in (1, 2, 4):
+        for m in (E + 2, 15, 40):
+            mask = synth.library_samples(L, E, [m], 1, seed)[0]
+            Q, idx, w, d2 = O.knn_table(x, E, 1, 0, cand=mask)
+            bf = _brute_knn_subset(xi, E, np.nonzero(mask)[0].tolist(), E + 1)
+            assert len(Q) == L - (E - 1)                     # every point is a query
+            for r, t in enumerate(Q):
+                assert idx[r].tolist() == bf[int(t)], (E, m, t)
+                assert all(mask[s] for s in idx[r])
+
+
+def test_subsample_masks_and_full_library_reduction():
+    masks = synth.library_samples(200, 3, [5, 50, 198], 4, 0)
+    assert masks.shape == (12, 200)
+    assert masks[:, :2].sum() == 0                            # only embedded points
+    np.testing.assert_array_equal(masks.sum(axis=1), [5] * 4 + [50] * 4 + [198] * 4)
+    assert len({m.tobytes() for m in masks[:4]}) == 4           # distinct draws
+    # a mask with every embedded point is the ordinary table and the ordinary rho
+    ts = synth.make("logistic64", cache=False).panel[:200]
+    full = np.ones((1, 1, 200), dtype=bool)
+    r_conv = O.ccm_convergence(ts, [2], [3], full, 1, 0, 10, k_max=4)
+    r_blk, _, _, _ = O.ccm_block(ts, [2], [3], 1, 0, 10, k_max=4)
+    np.testing.assert_array_equal(r_conv[:, 0, :], r_blk)
+
+
+def test_convergence_on_two_species():
+    """Skill of the driven series' library at recovering its driver rises with library
+    size and ends high (the behaviour the CCM convergence test looks for)."""
+    ts = synth.two_species(1000, 0)
+    sizes = [12, 50, 200, 800]
+    masks = synth.library_samples(1000, 2, sizes, 8, 1)
+    rho = O.ccm_convergence(ts, [1], [2], masks[None], 1, 0, 1, k_max=3)[0, :, 0]
+    curve = rho.reshape(len(sizes), 8).mean(axis=1)
+    assert np.all(np.diff(curve) > 0), curve
+    assert curve[-1] > 0.9 and curve[-1] - curve[0] > 0.1, curve
+    # the driver's library recovers the weakly coupled direction less well at every size
+    back = O.ccm_convergence(ts, [0], [2], masks[None], 1, 1, 1, k_max=3)[0, :, 0]
+    assert np.all(back.reshape(len(sizes), 8).mean(axis=1) < curve)
