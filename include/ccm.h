@@ -92,8 +92,9 @@ ccm_status ccm_embed(const float* ts, int64_t ld, int32_t L, const int32_t* ids,
  *   subtraction, product and sum rounded once, lag 0 first.
  *   Outputs, row-major [n_lib][L][k_max]:
  *     nbr_idx  neighbour time indices, nearest first;
- *     nbr_w    weights u_k / sum(u), u_k = exp(-d_k / d_1), d = sqrt(d^2) in FP32; when
- *              d_1 = 0, u_k = 1 where d_k = 0 and 0 elsewhere;
+ *     nbr_w    weights u_k / sum(u), u_k = exp(-d_k / d_1), with each selected neighbour's
+ *              distance d recomputed in FP64 from the series; when d_1 = 0, u_k = 1
+ *              where d_k = 0 and 0 elsewhere;
  *     nbr_d2   (nullable) the FP32 d^2 of each neighbour.
  *   Rows t outside the query set and slots beyond E + 1 are padding: idx = -1, w = 0,
  *   d2 = +inf.  A library whose E is out of [1, CCM_E_MAX], has E + 1 > k_max, or has
@@ -105,6 +106,22 @@ ccm_status ccm_knn(const float* ts, int64_t ld, int32_t L, const int32_t* lib_id
                    const int32_t* lib_E, int32_t n_lib, int32_t tau, int32_t Tp, int32_t k_max,
                    int32_t* nbr_idx, float* nbr_w, float* nbr_d2, void* ws, size_t ws_bytes,
                    void* stream);
+
+/*
+ * ccm_knn_subset -- ccm_knn over a library subsample, for the CCM convergence test (the
+ * original CCM definition recalled in Sec. III-A: predictions repeated with random
+ * library subsets of growing size).
+ *   cand_mask [n_lib][L]  (device, uint8) nonzero at the time indices library row i may
+ *                         take as neighbours; every point of the query set is still a
+ *                         query, and excluded from its own candidates.
+ *   Everything else as ccm_knn.  A library with fewer than E + 2 marked points in its
+ *   candidate set gets padding in every row.
+ * Errors: as ccm_knn, and EINVAL if cand_mask is NULL.  Workspace: none.
+ */
+ccm_status ccm_knn_subset(const float* ts, int64_t ld, int32_t L, const int32_t* lib_ids,
+                          const int32_t* lib_E, int32_t n_lib, int32_t tau, int32_t Tp,
+                          int32_t k_max, const uint8_t* cand_mask, int32_t* nbr_idx,
+                          float* nbr_w, float* nbr_d2, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * ccm_simplex_optE -- optimal embedding dimension per series by simplex projection

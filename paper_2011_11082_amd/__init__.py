@@ -29,8 +29,8 @@ PRECISION_FP32, PRECISION_BF16 = 0, 1
  OP_CROSSMAP_TARGET_E) = range(7)
 
 EXPORTED = (
-    "ccm_embed", "ccm_knn", "ccm_simplex_optE", "ccm_crossmap_rho", "ccm_crossmap_rho_backward",
-    "ccm_crossmap_rho_target_E", "ccm_workspace_size", "ccm_status_string", "ccm_last_error", "ccm_version",
+    "ccm_embed", "ccm_knn", "ccm_knn_subset", "ccm_simplex_optE", "ccm_crossmap_rho",
+    "ccm_crossmap_rho_backward", "ccm_crossmap_rho_target_E", "ccm_workspace_size", "ccm_status_string", "ccm_last_error", "ccm_version",
 )
 
 
@@ -61,6 +61,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     sig = {
         "ccm_embed": [_P, _I64, _I32, _P, _I32, _I32, _I32, _P, _P],
         "ccm_knn": [_P, _I64, _I32, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _SZ, _P],
+        "ccm_knn_subset": [_P, _I64, _I32, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P,
+                           _SZ, _P],
         "ccm_simplex_optE": [_P, _I64, _I32, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P,
                              _SZ, _P],
         "ccm_crossmap_rho": [_P, _I64, _I32, _P, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P,
@@ -150,8 +152,10 @@ def embed(ts: torch.Tensor, ids, E: int, tau: int = 1) -> torch.Tensor:
 
 
 def knn(ts: torch.Tensor, lib_ids, lib_E, tau: int = 1, Tp: int = 0, k_max: int = K_MAX,
-        want_d2: bool = True):
-    """Neighbour tables (idx int32, w float32, d2 float32 or None), each [n_lib][L][k_max]."""
+        want_d2: bool = True, cand_mask: Optional[torch.Tensor] = None):
+    """Neighbour tables (idx int32, w float32, d2 float32 or None), each [n_lib][L][k_max].
+    cand_mask (bool or uint8 [n_lib][L], optional): library subsample per row
+    (ccm_knn_subset)."""
     lib = load_library()
     ts, ld, L = _panel(ts)
     lib_ids = _i32(lib_ids, ts.device)
@@ -162,8 +166,15 @@ def knn(ts: torch.Tensor, lib_ids, lib_E, tau: int = 1, Tp: int = 0, k_max: int 
     idx = torch.empty((n, L, k_max), dtype=torch.int32, device=ts.device)
     w = torch.empty((n, L, k_max), dtype=torch.float32, device=ts.device)
     d2 = torch.empty((n, L, k_max), dtype=torch.float32, device=ts.device) if want_d2 else None
-    _check(lib.ccm_knn(_ptr(ts), ld, L, _ptr(lib_ids), _ptr(lib_E), n, tau, Tp, k_max, _ptr(idx),
-                       _ptr(w), _ptr(d2), None, 0, _stream()))
+    if cand_mask is None:
+        _check(lib.ccm_knn(_ptr(ts), ld, L, _ptr(lib_ids), _ptr(lib_E), n, tau, Tp, k_max,
+                           _ptr(idx), _ptr(w), _ptr(d2), None, 0, _stream()))
+    else:
+        m = torch.as_tensor(cand_mask, device=ts.device).to(torch.uint8).contiguous()
+        if m.shape != (n, L):
+            raise ValueError("cand_mask must be [n_lib][L]")
+        _check(lib.ccm_knn_subset(_ptr(ts), ld, L, _ptr(lib_ids), _ptr(lib_E), n, tau, Tp, k_max,
+                                  _ptr(m), _ptr(idx), _ptr(w), _ptr(d2), None, 0, _stream()))
     return idx, w, d2
 
 
@@ -254,6 +265,23 @@ def crossmap_rho_target_E(ts: torch.Tensor, nbr_idx: torch.Tensor, nbr_w: torch.
                                          E_lo, n_E, k_max, tau, _ptr(tgt_E), tgt0, n_tgt,
                                          _ptr(rho), _ptr(mom), _ptr(ws), nbytes, _stream()))
     return (rho, mom) if want_moments else rho
+
+
+def ccm_convergence(ts: torch.Tensor, lib_ids, lib_E, masks, tau: int = 1, tgt0: int = 0,
+                    n_tgt: Optional[int] = None, k_max: int = K_MAX):
+    """CCM convergence test: rho [n_lib][n_samp][n_tgt], library i's table at E_i built over
+    each candidate mask masks[i][r] (a random library subsample; every point is a query),
+    then the cross-map of every target.  One ccm_knn_subset call over the (library, sample)
+    rows and one ccm_crossmap_rho call."""
+    ts, _, L = _panel(ts)
+    masks = torch.as_tensor(masks, device=ts.device)
+    n_lib, n_samp = int(masks.shape[0]), int(masks.shape[1])
+    ids = _i32(lib_ids, ts.device).repeat_interleave(n_samp)
+    Es = _i32(lib_E, ts.device).repeat_interleave(n_samp)
+    idx, w, _ = knn(ts, ids, Es, tau, 0, k_max, want_d2=False,
+                    cand_mask=masks.reshape(n_lib * n_samp, L))
+    rho = crossmap_rho(ts, idx, w, Es, tau, tgt0, n_tgt)
+    return rho.reshape(n_lib, n_samp, -1)
 
 
 def crossmap_rho_backward(ts, lib_ts, nbr_idx, nbr_w, lib_E, pair_lib, pair_tgt, grad_rho,

@@ -12,8 +12,8 @@
 
 extern "C" {
 hipError_t ccm_launch_knn(const float* ts, int64_t ld, int L, const int* lib_ids, const int* lib_E,
-                          int n_lib, int tau, int Tp, int k_max, int* nbr_idx, float* nbr_w,
-                          float* nbr_d2, hipStream_t stream);
+                          int n_lib, int tau, int Tp, int k_max, const uint8_t* cand_mask,
+                          int* nbr_idx, float* nbr_w, float* nbr_d2, hipStream_t stream);
 hipError_t ccm_launch_simplex(const float* ts, int64_t ld, int L, const int* ids, int n, int E_min,
                               int E_max, int tau, int Tp, int mode, int* optE, float* rho_E,
                               double* rho64, hipStream_t stream);
@@ -189,13 +189,11 @@ ccm_status ccm_embed(const float* ts, int64_t ld, int32_t L, const int32_t* ids,
   return device_status(fn, ccm_launch_embed(ts, ld, L, ids, n, E, tau, emb, (hipStream_t)stream));
 }
 
-ccm_status ccm_knn(const float* ts, int64_t ld, int32_t L, const int32_t* lib_ids,
-                   const int32_t* lib_E, int32_t n_lib, int32_t tau, int32_t Tp, int32_t k_max,
-                   int32_t* nbr_idx, float* nbr_w, float* nbr_d2, void* ws, size_t ws_bytes,
-                   void* stream) {
-  (void)ws;
-  (void)ws_bytes;
-  const char* fn = "ccm_knn";
+namespace {
+ccm_status knn_common(const char* fn, const float* ts, int64_t ld, int32_t L,
+                      const int32_t* lib_ids, const int32_t* lib_E, int32_t n_lib, int32_t tau,
+                      int32_t Tp, int32_t k_max, const uint8_t* cand_mask, int32_t* nbr_idx,
+                      float* nbr_w, float* nbr_d2, void* stream) {
   ccm_status st = CCM_OK;
   if (!check_series(fn, &st, ts, ld, L, tau)) return st;
   if (n_lib < 0) return fail(CCM_EINVAL, fn, "n_lib < 0");
@@ -203,8 +201,30 @@ ccm_status ccm_knn(const float* ts, int64_t ld, int32_t L, const int32_t* lib_id
     return fail(CCM_EINVAL, fn, "NULL array argument");
   if (k_max < 2 || k_max > CCM_K_MAX) return fail(CCM_EINVAL, fn, "k_max outside [2, CCM_K_MAX]");
   if (Tp < 0 || Tp >= L) return fail(CCM_EINVAL, fn, "Tp outside [0, L)");
-  return device_status(fn, ccm_launch_knn(ts, ld, L, lib_ids, lib_E, n_lib, tau, Tp, k_max, nbr_idx,
-                                          nbr_w, nbr_d2, (hipStream_t)stream));
+  return device_status(fn, ccm_launch_knn(ts, ld, L, lib_ids, lib_E, n_lib, tau, Tp, k_max,
+                                          cand_mask, nbr_idx, nbr_w, nbr_d2, (hipStream_t)stream));
+}
+}  // namespace
+
+ccm_status ccm_knn(const float* ts, int64_t ld, int32_t L, const int32_t* lib_ids,
+                   const int32_t* lib_E, int32_t n_lib, int32_t tau, int32_t Tp, int32_t k_max,
+                   int32_t* nbr_idx, float* nbr_w, float* nbr_d2, void* ws, size_t ws_bytes,
+                   void* stream) {
+  (void)ws;
+  (void)ws_bytes;
+  return knn_common("ccm_knn", ts, ld, L, lib_ids, lib_E, n_lib, tau, Tp, k_max, nullptr, nbr_idx,
+                    nbr_w, nbr_d2, stream);
+}
+
+ccm_status ccm_knn_subset(const float* ts, int64_t ld, int32_t L, const int32_t* lib_ids,
+                          const int32_t* lib_E, int32_t n_lib, int32_t tau, int32_t Tp,
+                          int32_t k_max, const uint8_t* cand_mask, int32_t* nbr_idx,
+                          float* nbr_w, float* nbr_d2, void* ws, size_t ws_bytes, void* stream) {
+  (void)ws;
+  (void)ws_bytes;
+  if (n_lib > 0 && !cand_mask) return fail(CCM_EINVAL, "ccm_knn_subset", "cand_mask is NULL");
+  return knn_common("ccm_knn_subset", ts, ld, L, lib_ids, lib_E, n_lib, tau, Tp, k_max, cand_mask,
+                    nbr_idx, nbr_w, nbr_d2, stream);
 }
 
 ccm_status ccm_simplex_optE(const float* ts, int64_t ld, int32_t L, const int32_t* ids, int32_t n,

@@ -140,12 +140,14 @@ __device__ __forceinline__ float thr_float(uint64_t thr) {
 // follows inserts few candidates.  `key` holds the previous query's list (lanes 0..E) on
 // entry and the seeded list on exit.  Candidates run to `chi`; (E-1)*tau is the first.
 template <int E, bool TAU1, int NQ>
-__device__ __forceinline__ void seed_list(const float* x, int t, int tau, int chi, bool excl_self,
-                                          const float (&xq)[NQ], uint64_t& key, uint64_t& thr) {
+__device__ __forceinline__ void seed_list(const float* x, const uint8_t* mb, int t, int tau,
+                                          int chi, bool excl_self, const float (&xq)[NQ],
+                                          uint64_t& key, uint64_t& thr) {
   const int lane = lane_id();
   const int nb = lane <= E ? key_idx(key) : -1;
   const int s = nb + 1;
-  const bool ok = nb >= 0 && s <= chi && (!excl_self || s != t);
+  bool ok = nb >= 0 && s <= chi && (!excl_self || s != t);
+  if (mb) ok = ok && mb[ok ? s : 0] != 0;
   const int sc = ok ? s : (E - 1) * tau;
   float xs[E];
   lag_values<E, TAU1>(x, sc, tau, xs);
@@ -188,8 +190,9 @@ constexpr int kKnnThreads = 1024;
 // seeded from the previous query's list and all chunks are scanned in order; otherwise the
 // list starts empty and the window around t is scanned first.
 template <int E, bool TAU1>
-__device__ __forceinline__ void knn_query(const float* x, int t, int lo, int hi, int tau,
-                                          bool seeded, uint64_t& key, uint64_t& thr) {
+__device__ __forceinline__ void knn_query(const float* x, const uint8_t* mb, int t, int lo,
+                                          int hi, int tau, bool seeded, uint64_t& key,
+                                          uint64_t& thr) {
   const int lane = lane_id();
   float xq[kEMax];
 #pragma unroll
@@ -197,7 +200,7 @@ __device__ __forceinline__ void knn_query(const float* x, int t, int lo, int hi,
     xq[e] = e < E ? __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x[t - e * tau])))
                   : 0.0f;
   if (seeded) {
-    seed_list<E, TAU1, kEMax>(x, t, tau, hi, true, xq, key, thr);
+    seed_list<E, TAU1, kEMax>(x, mb, t, tau, hi, true, xq, key, thr);
   } else {
     key = ~0ull;
     thr = ~0ull;
@@ -218,7 +221,9 @@ __device__ __forceinline__ void knn_query(const float* x, int t, int lo, int hi,
       const float df = xq[e] - xs[e];
       acc = acc + df * df;
     }
-    const uint64_t cand = (inr && s != t) ? nkey(acc, s) : ~0ull;
+    bool adm = inr && s != t;
+    if (mb) adm = adm && mb[sc] != 0;   // library subsample: only marked candidates
+    const uint64_t cand = adm ? nkey(acc, s) : ~0ull;
     offer_chunk(cand, key, thr, E);
   }
 }
@@ -230,25 +235,40 @@ __device__ __forceinline__ void knn_query(const float* x, int t, int lo, int hi,
 __global__ __launch_bounds__(kKnnThreads) void knn_table_kernel(const float* __restrict__ ts, int64_t ld,
                                                         int L, const int* __restrict__ lib_ids,
                                                         const int* __restrict__ lib_E, int tau,
-                                                        int Tp, int k_max, int* __restrict__ nbr_idx,
+                                                        int Tp, int k_max,
+                                                        const uint8_t* __restrict__ cand_mask,
+                                                        int* __restrict__ nbr_idx,
                                                         float* __restrict__ nbr_w,
                                                         float* __restrict__ nbr_d2) {
   extern __shared__ float xbuf[];
   float* x = xbuf + kPad;
+  // optional candidate mask of this library (a library subsample), after the series
+  uint8_t* mb = cand_mask ? (uint8_t*)(xbuf + L + kPad) : nullptr;
+  __shared__ int n_adm;
   const int lib = blockIdx.x;
   const int sid = lib_ids[lib];
-  for (int t = threadIdx.x; t < L + kPad; t += blockDim.x)
-    xbuf[t] = t < kPad ? 0.0f : ts[(int64_t)(t - kPad) * ld + sid];
-  __syncthreads();
-
-  const int lane = lane_id();
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int nw = blockDim.x / kWave;
   const int E = __builtin_amdgcn_readfirstlane(lib_E[lib]);
   const int k = E + 1;
   const int lo = (E - 1) * tau;           // first point
   const int hi = L - 1 - Tp;              // last point with a future
-  const bool ok = E >= 1 && E <= kEMax && k <= k_max && (hi - lo + 1) - 1 >= k;
+  if (threadIdx.x == 0) n_adm = 0;
+  for (int t = threadIdx.x; t < L + kPad; t += blockDim.x)
+    xbuf[t] = t < kPad ? 0.0f : ts[(int64_t)(t - kPad) * ld + sid];
+  if (mb)
+    for (int t = threadIdx.x; t < L; t += blockDim.x) mb[t] = cand_mask[(size_t)lib * L + t];
+  __syncthreads();
+  bool ok = E >= 1 && E <= kEMax && k <= k_max && (hi - lo + 1) - 1 >= k;
+  if (mb && ok) {   // enough marked candidates for every query (one may be the query itself)
+    int c = 0;
+    for (int t = lo + threadIdx.x; t <= hi; t += blockDim.x) c += mb[t] != 0;
+    if (c) atomicAdd(&n_adm, c);
+    __syncthreads();
+    ok = n_adm - 1 >= k;
+  }
+
+  const int lane = lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int nw = blockDim.x / kWave;
   const size_t rowbase = (size_t)lib * L;
 
   // padding rows (outside [lo, hi], or every row of an unusable library)
@@ -273,9 +293,9 @@ __global__ __launch_bounds__(kKnnThreads) void knn_table_kernel(const float* __r
 #define CCM_E(EE)                                                 \
   case EE:                                                        \
     if (tau == 1)                                                 \
-      knn_query<EE, true>(x, t, lo, hi, tau, seeded, key, thr);   \
-    else                                                          \
-      knn_query<EE, false>(x, t, lo, hi, tau, seeded, key, thr);  \
+      knn_query<EE, true>(x, mb, t, lo, hi, tau, seeded, key, thr);  \
+    else                                                              \
+      knn_query<EE, false>(x, mb, t, lo, hi, tau, seeded, key, thr); \
     break;
       CCM_E(1) CCM_E(2) CCM_E(3) CCM_E(4) CCM_E(5) CCM_E(6) CCM_E(7) CCM_E(8) CCM_E(9) CCM_E(10)
       CCM_E(11) CCM_E(12) CCM_E(13) CCM_E(14) CCM_E(15) CCM_E(16) CCM_E(17) CCM_E(18) CCM_E(19)
@@ -319,7 +339,7 @@ __device__ __forceinline__ void seed_group(const float* x, int t, int tau, int c
     constexpr int E = ELO + G;
     const int qE = qbase + (E - 1) * tau;
     if (E >= E_lo && E <= E_hi && t - 1 >= qE)
-      seed_list<E, TAU1, EHI>(x, t, tau, chi, !half, xq, key[G], thr[G]);
+      seed_list<E, TAU1, EHI>(x, nullptr, t, tau, chi, !half, xq, key[G], thr[G]);
     seed_group<ELO, G + 1, NG, TAU1, EHI>(x, t, tau, chi, half, qbase, E_lo, E_hi, xq, key, thr);
   }
 }
@@ -520,15 +540,31 @@ __global__ void embed_kernel(const float* __restrict__ ts, int64_t ld, int L,
 }  // namespace ccm
 
 // ---- launchers (called from the C ABI) ----------------------------------------------
+namespace ccm {
+// The series copy (and mask) of a long series exceeds the default 64 KB of dynamic LDS.
+hipError_t allow_lds(const void* kernel, bool& done) {
+  if (done) return hipSuccess;
+  hipFuncAttributes fa;
+  hipError_t e = hipFuncGetAttributes(&fa, kernel);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          160 * 1024 - (int)fa.sharedSizeBytes);
+  if (e == hipSuccess) done = true;
+  return e;
+}
+}  // namespace ccm
+
 extern "C" hipError_t ccm_launch_knn(const float* ts, int64_t ld, int L, const int* lib_ids,
                                      const int* lib_E, int n_lib, int tau, int Tp, int k_max,
-                                     int* nbr_idx, float* nbr_w, float* nbr_d2,
-                                     hipStream_t stream) {
+                                     const uint8_t* cand_mask, int* nbr_idx, float* nbr_w,
+                                     float* nbr_d2, hipStream_t stream) {
   if (n_lib == 0) return hipSuccess;
-  size_t lds = (size_t)(L + ccm::kPad) * sizeof(float);
+  static bool attr = false;
+  hipError_t e = ccm::allow_lds((const void*)ccm::knn_table_kernel, attr);
+  if (e != hipSuccess) return e;
+  size_t lds = (size_t)(L + ccm::kPad) * sizeof(float) + (cand_mask ? (size_t)L : 0);
   hipLaunchKernelGGL(ccm::knn_table_kernel, dim3(n_lib), dim3(ccm::kKnnThreads), lds, stream, ts, ld,
-                     L, lib_ids,
-                     lib_E, tau, Tp, k_max, nbr_idx, nbr_w, nbr_d2);
+                     L, lib_ids, lib_E, tau, Tp, k_max, cand_mask, nbr_idx, nbr_w, nbr_d2);
   return hipGetLastError();
 }
 
@@ -537,6 +573,9 @@ extern "C" hipError_t ccm_launch_simplex(const float* ts, int64_t ld, int L, con
                                          int* optE, float* rho_E, double* rho64,
                                          hipStream_t stream) {
   if (n == 0) return hipSuccess;
+  static bool attr = false;
+  hipError_t e = ccm::allow_lds((const void*)ccm::simplex_kernel, attr);
+  if (e != hipSuccess) return e;
   size_t lds = (size_t)(L + ccm::kPad) * sizeof(float);
   hipLaunchKernelGGL(ccm::simplex_kernel, dim3(n, 3), dim3(ccm::kSimplexThreads), lds, stream, ts,
                      ld, L, ids, E_min, E_max, tau, Tp, mode, rho64);

@@ -132,3 +132,14 @@ def test_target_E_argument_errors_and_workspace():
     a = ccm.workspace_size(ccm.OP_CROSSMAP_TARGET_E, 1600, 20 * 512, 101729, 21)
     b = ccm.workspace_size(ccm.OP_CROSSMAP_FP32, 1600, 20 * 512, 101729, 21)
     assert a >= b + 101729 * 4 + ((101729 + 15) // 16 + 21) * 12
+
+
+def test_knn_subset_requires_a_mask():
+    lib = ccm.load_library()
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.ccm_knn_subset(fake, 8, 100, fake, fake, 2, 1, 0, 21, _null(), fake, fake, _null(),
+                              _null(), 0, _null()) == ccm.CCM_EINVAL
+    assert b"cand_mask" in lib.ccm_last_error()
+    # no libraries: nothing to do
+    assert lib.ccm_knn_subset(fake, 8, 100, fake, fake, 0, 1, 0, 21, _null(), fake, fake, _null(),
+                              _null(), 0, _null()) == ccm.CCM_OK

@@ -1,0 +1,100 @@
+"""GPU-vs-oracle parity of the CCM convergence test (tables over random library subsamples,
+ccm_knn_subset, then the cross-map), through the C ABI.
+
+The subsample masks are seeded inputs from synth.library_samples.  Indices and d^2 must be
+bit-identical to the oracle's, weights within 2e-6, rho within 1e-5."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+RHO_TOL = 1e-5
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ccm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2011_11082_amd as m
+
+    m.load_library()
+    return m
+
+
+def _cuda(a):
+    import torch
+
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+def test_subsampled_tables_bit_exact(ccm):
+    w = synth.make("ratenet1024")
+    ts = w.panel
+    L = ts.shape[0]
+    lib_ids, lib_E, masks = [], [], []
+    for sid, E in ((11, 2), (400, 7), (900, 13), (1020, 20)):
+        for m in (E + 2, 120, 900):
+            lib_ids.append(sid)
+            lib_E.append(E)
+            masks.append(synth.library_samples(L, E, [m], 1, sid)[0])
+    masks = np.array(masks)
+    _say("subsampled tables ratenet1024, 12 rows")
+    idx, wt, d2 = ccm.knn(_cuda(ts), lib_ids, lib_E, k_max=21, cand_mask=_cuda(masks))
+    idx, wt, d2 = idx.cpu().numpy(), wt.cpu().numpy(), d2.cpu().numpy()
+    idx_o, w_o, d2_o = O.knn(ts, lib_ids, lib_E, 1, 0, 21, cand_masks=masks)
+    bad = np.argwhere(idx != idx_o)
+    assert bad.size == 0, f"{len(bad)} index mismatches, first {bad[:3].tolist()}"
+    valid = idx_o >= 0
+    assert np.array_equal(d2[valid], d2_o[valid])
+    assert np.abs(wt.astype(np.float64) - w_o).max() < 2e-6
+    # neighbours come only from the subsample
+    for r in range(len(lib_ids)):
+        n = idx[r][idx[r] >= 0]
+        assert masks[r][n].all()
+
+
+def test_full_mask_equals_plain_tables_and_small_mask_pads(ccm):
+    w = synth.make("ratenet1024")
+    ts = _cuda(w.panel)
+    L = w.panel.shape[0]
+    ids, Es = [5, 6, 7], [4, 9, 3]
+    full = np.zeros((3, L), dtype=bool)
+    for r, E in enumerate(Es):
+        full[r, E - 1:] = True
+    full[2, :] = False
+    full[2, [10, 20, 30, 40]] = True            # 4 marked points < k + 1 = 5: padding
+    _say("full and too-small masks")
+    a = ccm.knn(ts, ids[:2], Es[:2], k_max=21)
+    b = ccm.knn(ts, ids, Es, k_max=21, cand_mask=_cuda(full))
+    for x, y in zip(a, b):
+        assert np.array_equal(x.cpu().numpy(), y[:2].cpu().numpy())
+    assert np.all(b[0][2].cpu().numpy() == -1) and np.all(b[1][2].cpu().numpy() == 0)
+    rho = ccm.crossmap_rho(ts, b[0], b[1], Es, n_tgt=50).cpu().numpy()
+    assert np.all(np.isnan(rho[2])) and np.all(np.isfinite(rho[:2]))
+
+
+def test_convergence_two_species(ccm):
+    ts = synth.two_species(1000, 0)
+    sizes = [12, 50, 200, 800]
+    masks = synth.library_samples(1000, 2, sizes, 8, 1)
+    _say("convergence two species, 32 subsamples")
+    rho = ccm.ccm_convergence(_cuda(ts), [1], [2], _cuda(masks[None]), tgt0=0, n_tgt=2,
+                              k_max=3).cpu().numpy()
+    rho_o = O.ccm_convergence(ts, [1], [2], masks[None], 1, 0, 2, k_max=3)
+    d = np.abs(rho.astype(np.float64) - rho_o)
+    print(f"convergence: |drho| max {d.max():.3e}")
+    assert d.max() < RHO_TOL
+    curve = rho[0, :, 0].reshape(len(sizes), 8).mean(axis=1)
+    assert np.all(np.diff(curve) > 0) and curve[-1] > 0.9, curve
