@@ -130,6 +130,8 @@ def main():
     ap.add_argument("--n-lib", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-convergence", action="store_true",
+                    help="skip the CCM convergence test (tables over library subsamples)")
     ap.add_argument("--no-target-E", action="store_true",
                     help="skip the per-target-E form (optE of every series + all-E tables)")
     ap.add_argument("--profile-steps", action="store_true",
@@ -308,6 +310,42 @@ def main():
             f"{tE['n_tables']} tables {tE['tables_all_E_ms']:.1f} ms, "
             f"cross-map {tE['crossmap_ms']:.1f} ms")
         del optE_all
+
+    # The CCM convergence test (not part of the step; reported beside it): every library's
+    # table at its optE over random library subsamples of growing size (7 sizes x 4 draws),
+    # then the cross-map of 1,024 evenly spaced targets.
+    if not args.no_convergence and not args.profile_steps:
+        sizes = [25, 50, 100, 200, 400, 800, 1500]
+        n_draw = 4
+        n_cv_tgt = 1024
+        masks = np.zeros((n_lib, len(sizes) * n_draw, L), dtype=bool)
+        for E in sorted(set(optE_np.tolist())):
+            rows = np.nonzero(optE_np == E)[0]
+            masks[rows] = synth.library_samples(L, int(E), sizes, n_draw, int(E))[None]
+        cols = np.arange(0, n_tgt, n_tgt // n_cv_tgt)[:n_cv_tgt] + wl.tgt0
+        Ysub = ts[:, torch.as_tensor(cols, device=dev)].contiguous()
+        m_dev = torch.as_tensor(masks, device=dev)
+        ids_rep = lib_ids.repeat_interleave(masks.shape[1])
+        E_rep = optE.repeat_interleave(masks.shape[1])
+        panel_cv = torch.cat([ts[:, lib_ids.long()], Ysub], dim=1).contiguous()
+        lib_cols = torch.arange(n_lib, dtype=torch.int32, device=dev).repeat_interleave(masks.shape[1])
+        for rep in range(2):   # one warm-up, one timed
+            ea = ev(); ea.record()
+            cidx, cw, _ = ccm.knn(panel_cv, lib_cols, E_rep, 1, 0, 21, want_d2=False,
+                                  cand_mask=m_dev.reshape(-1, L))
+            eb = ev(); eb.record()
+            crho = ccm.crossmap_rho(panel_cv, cidx, cw, E_rep, 1, n_lib, n_cv_tgt)
+            ec = ev(); ec.record()
+            torch.cuda.synchronize()
+        curve = crho.reshape(n_lib, len(sizes), n_draw, n_cv_tgt).nanmean(dim=(0, 2, 3))
+        cv = {"n_tables": int(cidx.shape[0]), "library_sizes": sizes, "draws_per_size": n_draw,
+              "n_tgt": n_cv_tgt, "tables_ms": round(ea.elapsed_time(eb), 3),
+              "crossmap_ms": round(eb.elapsed_time(ec), 3),
+              "mean_rho_by_size": [round(float(v), 4) for v in curve.cpu()]}
+        res["convergence"] = cv
+        log(f"convergence: {cv['n_tables']} subsampled tables {cv['tables_ms']:.1f} ms, "
+            f"cross-map {cv['crossmap_ms']:.1f} ms, mean rho by size {cv['mean_rho_by_size']}")
+        del cidx, cw, crho, m_dev, panel_cv
 
     if not args.no_cpu_baseline and not args.profile_steps:
         log("timing the CPU oracle on a bounded sample")
