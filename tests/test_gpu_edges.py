@@ -1,0 +1,126 @@
+"""Edge cases of the HIP path against the oracle, through the C ABI: lag tau = 2 in the
+cross-map (both precisions), the largest series the FP32 tile holds (L = 2475), long series
+in the table and optE kernels (sampled query rows), and empty inputs."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ccm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2011_11082_amd as m
+
+    m.load_library()
+    return m
+
+
+def _cuda(a):
+    import torch
+
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+def _check_rho(rho_g, rho_o, label, tol):
+    assert np.array_equal(np.isnan(rho_g), np.isnan(rho_o)), f"{label}: NaN pattern differs"
+    d = np.abs(rho_g.astype(np.float64) - rho_o)[~np.isnan(rho_o)]
+    print(f"{label}: |drho| max {d.max():.3e}")
+    assert d.max() < tol, f"{label}: max |drho| {d.max()}"
+
+
+def test_crossmap_tau2_both_precisions(ccm):
+    w = synth.make("ratenet1024")
+    ts = w.panel
+    lib_ids = np.array([2, 90, 333, 700, 1001, 512], dtype=np.int32)
+    lib_E = np.array([1, 3, 8, 12, 20, 5], dtype=np.int32)
+    tgt0, n_tgt = 3, 77
+    _say("crossmap tau=2, 6 libraries x 77 targets")
+    idx, wt, _ = ccm.knn(_cuda(ts), lib_ids, lib_E, tau=2, k_max=21)
+    idx_o, w_o, _ = O.knn(ts, lib_ids, lib_E, 2, 0, 21)
+    assert np.array_equal(idx.cpu().numpy(), idx_o)
+    rho_o = O.crossmap_rho(ts, idx_o, w_o, lib_E, 2, tgt0, n_tgt)
+    r32 = ccm.crossmap_rho(_cuda(ts), idx, wt, lib_E, tau=2, tgt0=tgt0, n_tgt=n_tgt)
+    _check_rho(r32.cpu().numpy(), rho_o, "tau=2 FP32", 1e-5)
+    r16 = ccm.crossmap_rho(_cuda(ts), idx, wt, lib_E, tau=2, tgt0=tgt0, n_tgt=n_tgt,
+                           precision=ccm.PRECISION_BF16)
+    _check_rho(r16.cpu().numpy(), rho_o, "tau=2 BF16", 5e-3)
+
+
+def test_crossmap_at_the_largest_fp32_tile(ccm):
+    L = 2475                                  # L * 64 B + the column sums fill the 160 KB LDS
+    rng = np.random.default_rng(41)
+    ts = np.cumsum(rng.standard_normal((L, 40)), axis=0).astype(np.float32)
+    ts = (ts - ts.mean(0)) / ts.std(0)
+    lib_ids, lib_E = [0, 7, 33], np.array([2, 5, 9], dtype=np.int32)
+    _say("crossmap L=2475, 3 libraries x 40 targets")
+    idx, wt, _ = ccm.knn(_cuda(ts), lib_ids, lib_E, k_max=10)
+    rho = ccm.crossmap_rho(_cuda(ts), idx, wt, lib_E).cpu().numpy()
+    rho_o, idx_o, _, _ = O.ccm_block(ts, lib_ids, lib_E, 1, 0, 40, k_max=10)
+    assert np.array_equal(idx.cpu().numpy(), idx_o)
+    _check_rho(rho, rho_o, "L=2475", 1e-5)
+
+
+def test_long_series_tables_and_optE(ccm):
+    L = 16384                                  # the largest L the ABI accepts
+    rng = np.random.default_rng(42)
+    x = np.sin(0.05 * np.arange(L)) + 0.3 * rng.standard_normal(L)
+    ts = np.stack([x, np.roll(x, 7)], axis=1).astype(np.float32)
+    E = 3
+    _say("knn L=16384 E=3, sampled rows")
+    idx, wt, d2 = ccm.knn(_cuda(ts), [0], [E], k_max=4)
+    idx, wt, d2 = idx.cpu().numpy()[0], wt.cpu().numpy()[0], d2.cpu().numpy()[0]
+    Q, C, _ = O.point_sets(L, E, 1, 0)
+    q = Q[::331]
+    D2 = O.sqdist_fp32(ts[:, 0], q, C, E, 1)
+    idx_o, d2_o = O.select_knn(D2, q, C, E + 1, True)
+    w_o = O.weights_rows_fp64(ts[:, 0], q, idx_o, E, 1)
+    assert np.array_equal(idx[q], idx_o)
+    assert np.array_equal(d2[q], d2_o)
+    assert np.abs(wt[q].astype(np.float64) - w_o).max() < 2e-6
+    assert np.all(idx[: E - 1] == -1)
+    # optE at L = 16384 on an exactly periodic series with distinct phase values: every
+    # query has exact repeats as neighbours (d_1 = 0), so each prediction is exact and every
+    # skill is 1 (which E wins is then decided by rounding: all skills tie within 1e-6)
+    _say("optE L=16384 periodic, E=1..6")
+    per = np.stack([synth.periodic(37, L, rng), synth.periodic(53, L, rng)], axis=1)
+    optE, rho_E = ccm.simplex_optE(_cuda(per), [0, 1], 1, 6, 1, 1)
+    assert np.abs(rho_E.cpu().numpy() - 1.0).max() < 1e-6
+    assert np.all((optE.cpu().numpy() >= 1) & (optE.cpu().numpy() <= 6))
+    # and the oracle on a 3,000-step prefix of the noisy pair, every skill
+    _say("optE L=3000 E=1..4")
+    ts3 = np.ascontiguousarray(ts[:3000])
+    optE, rho_E = ccm.simplex_optE(_cuda(ts3), [0, 1], 1, 4, 1, 1)
+    oE, oR, _ = O.simplex_optE(ts3, [0, 1], 1, 4, 1, 1)
+    assert np.array_equal(optE.cpu().numpy(), oE)
+    assert np.abs(rho_E.cpu().numpy() - oR).max() < 1e-5
+
+
+def test_empty_inputs(ccm):
+    import torch
+
+    ts = _cuda(synth.make("logistic64").panel)
+    _say("empty inputs")
+    idx, wt, d2 = ccm.knn(ts, np.zeros(0, np.int32), np.zeros(0, np.int32), k_max=4)
+    assert idx.shape == (0, ts.shape[0], 4)
+    optE, rho_E = ccm.simplex_optE(ts, np.zeros(0, np.int32), 1, 5, 1, 1)
+    assert optE.numel() == 0
+    idx, wt, _ = ccm.knn(ts, [0, 1], [2, 3], k_max=4)
+    rho = ccm.crossmap_rho(ts, idx, wt, [2, 3], tgt0=10, n_tgt=0)
+    assert rho.shape == (2, 0)
+    rho = ccm.crossmap_rho(ts, idx, wt, [2, 3], tgt0=10, n_tgt=0, precision=ccm.PRECISION_BF16)
+    assert rho.shape == (2, 0)
+    torch.cuda.synchronize()
