@@ -130,6 +130,8 @@ def main():
     ap.add_argument("--n-lib", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint (gradient of rho over library-target pairs)")
     ap.add_argument("--no-convergence", action="store_true",
                     help="skip the CCM convergence test (tables over library subsamples)")
     ap.add_argument("--no-target-E", action="store_true",
@@ -346,6 +348,28 @@ def main():
         log(f"convergence: {cv['n_tables']} subsampled tables {cv['tables_ms']:.1f} ms, "
             f"cross-map {cv['crossmap_ms']:.1f} ms, mean rho by size {cv['mean_rho_by_size']}")
         del cidx, cw, crho, m_dev, panel_cv
+
+    # The adjoint (not part of the step; reported beside it): d rho / d (targets, libraries)
+    # with the neighbour sets fixed, for 4,096 seeded (library, target) pairs of this block.
+    if not args.no_adjoint and not args.profile_steps:
+        rng = np.random.default_rng(45)
+        P = 4096
+        prow = torch.as_tensor(rng.integers(0, n_lib, size=P).astype(np.int32), device=dev)
+        ptgt = torch.as_tensor(rng.integers(0, n_tgt, size=P).astype(np.int32) + wl.tgt0,
+                               device=dev)
+        X = ts[:, lib_ids.long()].t().contiguous()
+        grho = torch.ones(P, dtype=torch.float32, device=dev)
+        gts = torch.zeros_like(ts)
+        glib = torch.zeros_like(X)
+        for rep in range(2):   # one warm-up, one timed
+            ea = ev(); ea.record()
+            ccm.crossmap_rho_backward(ts, X, idx, w, optE, prow, ptgt, grho, 1, gts, glib)
+            eb = ev(); eb.record()
+            torch.cuda.synchronize()
+        res["adjoint"] = {"pairs": P, "backward_ms": round(ea.elapsed_time(eb), 3),
+                          "us_per_pair": round(ea.elapsed_time(eb) * 1e3 / P, 2)}
+        log(f"adjoint: {P} pairs backward {ea.elapsed_time(eb):.1f} ms")
+        del X, gts, glib
 
     if not args.no_cpu_baseline and not args.profile_steps:
         log("timing the CPU oracle on a bounded sample")

@@ -202,7 +202,9 @@ ccm_status ccm_crossmap_rho_target_E(const float* ts, int64_t ld, int32_t L,
  *   The gradient through a zero distance (d_k = 0 or d_1 = 0) is taken as 0.  Pairs whose
  *   rho is NaN contribute nothing.  Accumulation order is fixed (no atomics), so results
  *   are deterministic.
- * Errors: EINVAL, ERANGE, EWORKSPACE.  Workspace: CCM_OP_CROSSMAP_BACKWARD.
+ *   The tables' rows must hold distinct neighbours (as ccm_knn writes them).
+ * Errors: EINVAL, ERANGE, EWORKSPACE.  Workspace: ccm_workspace_size(CCM_OP_CROSSMAP_BACKWARD,
+ * L, n_lib, n_pairs, k_max).
  */
 ccm_status ccm_crossmap_rho_backward(const float* ts, int64_t ld, int32_t L, const float* lib_ts,
                                      const int32_t* nbr_idx, const float* nbr_w,

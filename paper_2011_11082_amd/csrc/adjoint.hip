@@ -19,10 +19,11 @@
 // gfx950 design: no atomics, fixed summation order (deterministic results).  Kernel 1:
 // one workgroup per pair recomputes yhat and the FP64 Pearson pieces and stores H, Gy.
 // Kernel 2: one thread per (pair, t) turns wbar into distance coefficients (distances
-// recomputed in FP64 from the library series).  Kernel 3: one thread per (pair, s) gathers
-// everything that lands on time s by scanning the pair's table (the transpose of the
-// neighbour relation, without building it).  Kernel 4: one thread per s adds the pairs'
-// contributions in pair order into the target and library gradients.
+// recomputed in FP64 from the library series).  Kernel 3: one workgroup per library builds
+// the transposed neighbour relation (for each time s, the table entries whose neighbour is
+// s, in table order).  Kernel 4: one thread per (pair, s) gathers everything that lands on
+// time s from those lists, O(E k) per (pair, s).  Kernel 5: one thread per s adds the
+// pairs' contributions in pair order into the target and library gradients.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -174,12 +175,74 @@ __global__ __launch_bounds__(256) void bw_coef_kernel(
 }
 
 // Contributions of pair p to time s: target (tc) and library (lc).  One thread per (p, s).
+// Transposed neighbour relation of each library's table: for every time s, the entries
+// (t, m) with n_m(t) = s, in increasing (t, m) order, packed as t * 32 + m.  Counts and
+// offsets in LDS; one wave then walks the rows in order (the k neighbours of a row are
+// distinct, so its lanes never write the same list), which keeps the order deterministic.
+constexpr int kTrThreads = 256;
+
+__global__ __launch_bounds__(kTrThreads) void bw_transpose_kernel(
+    const int* __restrict__ nbr_idx, const int* __restrict__ lib_E, int L, int k_max, int tau,
+    int* __restrict__ csr_off, int* __restrict__ csr_ent) {
+  extern __shared__ int cnt[];          // [L + 1], then chunk sums [kTrThreads]
+  int* csum = cnt + L + 1;
+  const int i = blockIdx.x;
+  const int E = lib_E[i];
+  const int k = E + 1;
+  const bool ok = E >= 1 && E <= kEMax && k <= k_max;
+  const int lo = ok ? (E - 1) * tau : L;
+  for (int q = threadIdx.x; q <= L; q += blockDim.x) cnt[q] = 0;
+  __syncthreads();
+  const int* tab = nbr_idx + (size_t)i * L * k_max;
+  for (int q = threadIdx.x; q < (L - lo) * k; q += blockDim.x) {
+    const int t = lo + q / k, m = q % k;
+    const int s = tab[(size_t)t * k_max + m];
+    if (s >= 0 && s < L) atomicAdd(&cnt[s], 1);
+  }
+  __syncthreads();
+  // exclusive scan of cnt[0..L): per-thread chunks, then the chunk sums
+  const int chunk = (L + kTrThreads - 1) / kTrThreads;
+  const int c0 = min((int)threadIdx.x * chunk, L), c1 = min(c0 + chunk, L);
+  int acc = 0;
+  for (int q = c0; q < c1; ++q) {
+    const int c = cnt[q];
+    cnt[q] = acc;
+    acc += c;
+  }
+  csum[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int th = 0; th < kTrThreads; ++th) {
+      const int c = csum[th];
+      csum[th] = run;
+      run += c;
+    }
+    cnt[L] = run;
+  }
+  __syncthreads();
+  for (int q = c0; q < c1; ++q) cnt[q] += csum[threadIdx.x];
+  __syncthreads();
+  int* off = csr_off + (size_t)i * (L + 1);
+  for (int q = threadIdx.x; q <= L; q += blockDim.x) off[q] = cnt[q];
+  __syncthreads();
+  int* ent = csr_ent + (size_t)i * L * k_max;
+  if (threadIdx.x < kWave) {
+    const int lane = threadIdx.x;
+    for (int t = lo; t < L; ++t) {
+      const int s = lane < k ? tab[(size_t)t * k_max + lane] : -1;
+      if (s >= 0 && s < L) ent[cnt[s]++] = t * 32 + lane;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void bw_scatter_kernel(
     const float* __restrict__ ts, int64_t ld, int L, const float* __restrict__ lib_ts,
     const int* __restrict__ nbr_idx, const float* __restrict__ nbr_w, const int* __restrict__ lib_E,
     int k_max, int tau, const int* __restrict__ pair_lib, int n_pairs, const float* __restrict__ H,
     const float* __restrict__ Gy, const int* __restrict__ pair_ok, const float* __restrict__ coef,
-    float* __restrict__ tc, float* __restrict__ lc) {
+    const int* __restrict__ csr_off, const int* __restrict__ csr_ent, float* __restrict__ tc,
+    float* __restrict__ lc) {
   const int p = blockIdx.y;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= L) return;
@@ -197,29 +260,30 @@ __global__ __launch_bounds__(256) void bw_scatter_kernel(
   const float* x = lib_ts + (size_t)i * L;
   const float* hp = H + (size_t)p * L;
   const float* co = coef + (size_t)p * L * k_max;
+  const int* off = csr_off + (size_t)i * (L + 1);
+  const int* ent = csr_ent + (size_t)i * L * k_max;
+  const float* wrow = nbr_w + (size_t)i * L * k_max;
   const double xs = x[s];
   double T = s >= lo ? (double)Gy[(size_t)p * L + s] : 0.0;
   double Lb = 0.0;
-  // s as a lag coordinate of query t = s + e tau
+  // s as lag coordinate e of query t = s + e tau
   for (int e = 0; e < E; ++e) {
     const int t = s + e * tau;
     if (t < lo || t >= L) continue;
     const int* ri = nbr_idx + ((size_t)i * L + t) * k_max;
     for (int m = 0; m < k; ++m) Lb += (double)co[(size_t)t * k_max + m] * (xs - (double)x[ri[m] - e * tau]);
   }
-  // s as the neighbour (target gather) or a lag coordinate of a neighbour
-  const int span = (E - 1) * tau;
-  for (int t = lo; t < L; ++t) {
-    const int* ri = nbr_idx + ((size_t)i * L + t) * k_max;
-    const float* rw = nbr_w + ((size_t)i * L + t) * k_max;
-    for (int m = 0; m < k; ++m) {
-      const int dlt = ri[m] - s;
-      if (dlt < 0 || dlt > span) continue;
-      if (dlt == 0) T += (double)rw[m] * (double)hp[t];
-      if (dlt % tau == 0) {
-        const int e = dlt / tau;
-        Lb -= (double)co[(size_t)t * k_max + m] * ((double)x[t - e * tau] - xs);
-      }
+  // s as a neighbour (the looked-up target value; lag 0 of the neighbour's point) and as
+  // lag coordinate e >= 1 of a neighbour n = s + e tau: the transposed lists of s + e tau
+  for (int e = 0; e < E; ++e) {
+    const int n = s + e * tau;
+    if (n >= L) break;
+    for (int q = off[n]; q < off[n + 1]; ++q) {
+      const int v = ent[q];
+      const int t = v >> 5, m = v & 31;
+      if (t < lo || t >= L || m >= k) continue;   // only a malformed table (repeated neighbours)
+      if (e == 0) T += (double)wrow[(size_t)t * k_max + m] * (double)hp[t];
+      Lb -= (double)co[(size_t)t * k_max + m] * ((double)x[t - e * tau] - xs);
     }
   }
   tco[s] = (float)T;
@@ -243,11 +307,14 @@ __global__ void bw_reduce_kernel(int64_t ld, int L, const int* __restrict__ pair
 
 }  // namespace ccm
 
-extern "C" size_t ccm_backward_ws_bytes(int L, int n_pairs, int k_max) {
-  // yhat, H, Gy, tc, lc: [P][L] floats; coef: [P][L][k_max] floats; pair_ok: [P] ints
-  const size_t a = (size_t)n_pairs * L * 4;
-  return 5 * ((a + 255) & ~(size_t)255) + (((size_t)n_pairs * L * k_max * 4 + 255) & ~(size_t)255) +
-         (((size_t)n_pairs * 4 + 255) & ~(size_t)255);
+static size_t up256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+extern "C" size_t ccm_backward_ws_bytes(int L, int n_lib, int n_pairs, int k_max) {
+  // yhat, H, Gy, tc, lc: [P][L] floats; coef: [P][L][k_max] floats; pair_ok: [P] ints;
+  // transposed tables: offsets [n_lib][L + 1], entries [n_lib][L][k_max] ints
+  const size_t a = up256((size_t)n_pairs * L * 4);
+  return 5 * a + up256((size_t)n_pairs * L * k_max * 4) + up256((size_t)n_pairs * 4) +
+         up256((size_t)n_lib * (L + 1) * 4) + up256((size_t)n_lib * L * k_max * 4);
 }
 
 extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, const float* lib_ts,
@@ -257,7 +324,7 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
                                           float* grad_ts, float* grad_lib, void* ws,
                                           hipStream_t stream) {
   if (n_pairs == 0) return hipSuccess;
-  const size_t a = (((size_t)n_pairs * L * 4) + 255) & ~(size_t)255;
+  const size_t a = up256((size_t)n_pairs * L * 4);
   char* base = (char*)ws;
   float* yhat = (float*)base;
   float* H = (float*)(base + a);
@@ -265,7 +332,24 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
   float* tc = (float*)(base + 3 * a);
   float* lc = (float*)(base + 4 * a);
   float* coef = (float*)(base + 5 * a);
-  int* pair_ok = (int*)(base + 5 * a + ((((size_t)n_pairs * L * k_max * 4) + 255) & ~(size_t)255));
+  char* after_coef = base + 5 * a + up256((size_t)n_pairs * L * k_max * 4);
+  int* pair_ok = (int*)after_coef;
+  int* csr_off = (int*)(after_coef + up256((size_t)n_pairs * 4));
+  int* csr_ent = (int*)((char*)csr_off + up256((size_t)n_lib * (L + 1) * 4));
+  static bool attr = false;
+  if (!attr) {
+    hipFuncAttributes fa;
+    hipError_t e = hipFuncGetAttributes(&fa, (const void*)ccm::bw_transpose_kernel);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)ccm::bw_transpose_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024 - (int)fa.sharedSizeBytes);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(ccm::bw_transpose_kernel, dim3(n_lib), dim3(ccm::kTrThreads),
+                     (size_t)(L + 1 + ccm::kTrThreads) * sizeof(int), stream, nbr_idx, lib_E, L,
+                     k_max, tau, csr_off, csr_ent);
   hipLaunchKernelGGL(ccm::bw_pair_kernel, dim3(n_pairs), dim3(ccm::kBwThreads), 0, stream, ts, ld, L,
                      nbr_idx, nbr_w, lib_E, n_lib, k_max, tau, pair_lib, pair_tgt, grad_rho, yhat, H,
                      Gy, pair_ok);
@@ -275,7 +359,7 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
                      pair_ok, coef);
   hipLaunchKernelGGL(ccm::bw_scatter_kernel, dim3((L + 255) / 256, n_pairs), dim3(256), 0, stream, ts,
                      ld, L, lib_ts, nbr_idx, nbr_w, lib_E, k_max, tau, pair_lib, n_pairs, H, Gy,
-                     pair_ok, coef, tc, lc);
+                     pair_ok, coef, csr_off, csr_ent, tc, lc);
   hipLaunchKernelGGL(ccm::bw_reduce_kernel, dim3((L + 255) / 256), dim3(256), 0, stream, ld, L,
                      pair_lib, pair_tgt, n_pairs, pair_ok, tc, lc, grad_ts, grad_lib);
   return hipGetLastError();

@@ -37,7 +37,7 @@ hipError_t ccm_launch_crossmap_bf16(const float* ts, int64_t ld, int L, int tau,
                                     int n_lib, int k_max, float* rho, double* moments, uint16_t* yt,
                                     uint32_t* ent, int* stage_off, int* lib_k, int* order,
                                     hipStream_t stream);
-size_t ccm_backward_ws_bytes(int L, int n_pairs, int k_max);
+size_t ccm_backward_ws_bytes(int L, int n_lib, int n_pairs, int k_max);
 hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, const float* lib_ts,
                                const int* nbr_idx, const float* nbr_w, const int* lib_E, int n_lib,
                                int k_max, int tau, const int* pair_lib, const int* pair_tgt,
@@ -170,7 +170,7 @@ ccm_status ccm_workspace_size(int32_t op, int32_t L, int32_t n_lib, int32_t n_tg
       *bytes = target_E_ws(L, n_lib, n_tgt, k_max).total;
       return CCM_OK;
     case CCM_OP_CROSSMAP_BACKWARD:  // n_tgt = number of pairs
-      *bytes = ccm_backward_ws_bytes(L, n_tgt, k_max);
+      *bytes = ccm_backward_ws_bytes(L, n_lib, n_tgt, k_max);
       return CCM_OK;
     default:
       return fail(CCM_EINVAL, "ccm_workspace_size", "unknown op");
@@ -343,7 +343,7 @@ ccm_status ccm_crossmap_rho_backward(const float* ts, int64_t ld, int32_t L, con
   if (!lib_ts || !nbr_idx || !nbr_w || !lib_E || !pair_lib || !pair_tgt || !grad_rho)
     return fail(CCM_EINVAL, fn, "NULL array argument");
   if (!grad_ts && !grad_lib) return fail(CCM_EINVAL, fn, "both gradients are NULL");
-  const size_t need = ccm_backward_ws_bytes(L, n_pairs, k_max);
+  const size_t need = ccm_backward_ws_bytes(L, n_lib, n_pairs, k_max);
   if (!ws || ws_bytes < need) return fail(CCM_EWORKSPACE, fn, "workspace too small");
   return device_status(fn, ccm_launch_backward(ts, ld, L, lib_ts, nbr_idx, nbr_w, lib_E, n_lib,
                                                k_max, tau, pair_lib, pair_tgt, grad_rho, n_pairs,
