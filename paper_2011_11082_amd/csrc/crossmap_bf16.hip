@@ -11,9 +11,12 @@
 // form is bound by MFMA throughput.
 //
 // gfx950 design:
-//   * workgroup = 4 waves = 2 libraries (sorted by E) x one tile of 128 targets; each wave
-//     owns 64 rows of a 128-row chunk of its library against the 128 targets: a 64 x 128
-//     FP32 accumulator (2 x 4 tiles of v_mfma_f32_32x32x16_bf16).
+//   * workgroup = 4 waves = 2 libraries (sorted by E) x one tile of 64 targets; each wave
+//     owns 64 rows of a 128-row chunk of its library against the 64 targets: a 64 x 64
+//     FP32 accumulator (2 x 2 tiles of v_mfma_f32_32x32x16_bf16).  With the FP64 moment
+//     sums in registers the workgroup needs under 80 KB of LDS and 256 registers per lane,
+//     so two workgroups share a CU and one's barriers and latencies overlap the other's
+//     products.
 //   * K (the neighbour time s) advances in stages of 64: the workgroup stages Y^T[128][64]
 //     BF16 in LDS (double-buffered, loaded two stages ahead through registers) and each wave
 //     scatters the nonzeros of its 64 rows into its own zeroed A tile [64][64]; after its
@@ -36,7 +39,7 @@ namespace ccm {
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 
-constexpr int kBTN = 128;     // targets per tile
+constexpr int kBTN = 64;      // targets per tile
 constexpr int kBRows = 128;   // rows of A per chunk
 constexpr int kHalf = 64;     // rows of A per wave
 constexpr int kStage = 64;    // K per stage
@@ -125,19 +128,17 @@ __global__ __launch_bounds__(kBRows) void bf16_entries_kernel(
       }
 }
 
-__global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
+__global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
     const float* __restrict__ ts, int64_t ld, int L, int tau, int tgt0, int n_tgt, int Lpad,
     const uint16_t* __restrict__ yt, const uint32_t* __restrict__ ent,
     const int* __restrict__ stage_off, const int* __restrict__ order, const int* __restrict__ lib_k,
     int n_lib, int nchunk_max, int nst, float* __restrict__ rho, double* __restrict__ moments) {
   extern __shared__ __align__(16) char smem[];
-  // B: two stages of Yt [128 targets][64 s] BF16 (16 KB each); A: per wave [64 rows][64 s];
-  // moments: per wave [5][4][64] FP64.
+  // B: two stages of Yt [64 targets][64 s] BF16 (9 KB each); A: per wave [64 rows][64 s]
   uint16_t* Bs = (uint16_t*)smem;
   uint16_t* As = (uint16_t*)(smem + 2 * kBTN * kRS * 2);
-  double* momb = (double*)(smem + 2 * kBTN * kRS * 2 + 4 * kHalf * kRS * 2);
   // the current chunk's sorted entries and stage offsets of both libraries
-  uint32_t* Es = (uint32_t*)(momb + 4 * 5 * 4 * kWave);
+  uint32_t* Es = (uint32_t*)(smem + 2 * kBTN * kRS * 2 + 4 * kHalf * kRS * 2);
   int* Ss = (int*)(Es + 2 * kBRows * kKMax);
   const int lane = lane_id();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -157,24 +158,25 @@ __global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
   if (lane == 0) s_nchunk[wave] = nchunk;
   uint16_t* Aw = As + (size_t)wave * kHalf * kRS;
   for (int q = lane; q < kHalf * kRS / 2; q += kWave) ((uint32_t*)Aw)[q] = 0u;
-  double* mom = momb + (size_t)wave * 5 * 4 * kWave;
+  // FP64 moment sums of this lane's two columns: y, y^2, yhat, yhat^2, y * yhat
+  double M[5][2];
 #pragma unroll
-  for (int q = 0; q < 20; ++q) mom[q * kWave + lane] = 0.0;
+  for (int q = 0; q < 5; ++q) M[q][0] = M[q][1] = 0.0;
   __syncthreads();
   const int nch_all = max(max(s_nchunk[0], s_nchunk[1]), max(s_nchunk[2], s_nchunk[3]));
 
-  // B stage loader: thread -> (target row r = tid/2, half h = tid%2): 64 bytes
-  const int br = threadIdx.x >> 1;
-  const int bh = threadIdx.x & 1;
-  const uint16_t* ysrc = yt + (size_t)(j0 + br) * Lpad + bh * 32;
+  // B stage loader: thread -> (target row r = tid/4, quarter q = tid%4): 32 bytes
+  const int br = threadIdx.x >> 2;
+  const int bq = threadIdx.x & 3;
+  const uint16_t* ysrc = yt + (size_t)(j0 + br) * Lpad + bq * 16;
   const bool brow_ok = j0 + br < n_tgt;
 
   for (int c = 0; c < nch_all; ++c) {
-    f32x16 acc[2][4];
+    f32x16 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+      for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
     const bool mine = c < nchunk;
@@ -190,16 +192,16 @@ __global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
       for (int q = half * kWave + lane; q < ne; q += 2 * kWave) eo[q] = eg[q];
     }
     // B stages travel through registers two stages ahead of their use
-    uint4 breg[4], breg2[4];
+    uint4 breg[2], breg2[2];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 2; ++q) {
       breg[q] = brow_ok ? *(const uint4*)(ysrc + q * 8) : uint4{0, 0, 0, 0};
       breg2[q] = (brow_ok && nst > 1) ? *(const uint4*)(ysrc + kStage + q * 8) : uint4{0, 0, 0, 0};
     }
     __syncthreads();  // staged entries visible to both waves of each library
     // one stage; R holds this stage's B rows and is reloaded with stage st + 2 once stored,
     // so the two register sets alternate without copies
-    auto stage = [&](int st, uint4 (&R)[4]) {
+    auto stage = [&](int st, uint4 (&R)[2]) {
       const int buf = st & 1;
       // scatter this wave's nonzeros of the stage (rows of its half only)
       int e0 = 0, e1 = 0;
@@ -213,29 +215,29 @@ __global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
         if ((row >> 6) == half) Aw[(row & 63) * kRS + ((v >> 7) & 63)] = (uint16_t)(v >> 16);
       }
       {
-        uint16_t* dst = Bs + (size_t)buf * kBTN * kRS + br * kRS + bh * 32;
+        uint16_t* dst = Bs + (size_t)buf * kBTN * kRS + br * kRS + bq * 16;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) *(uint4*)(dst + q * 8) = R[q];
+        for (int q = 0; q < 2; ++q) *(uint4*)(dst + q * 8) = R[q];
       }
       __syncthreads();  // B stage `buf` complete; the other buffer is free
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < 2; ++q)
         R[q] = (brow_ok && st + 2 < nst) ? *(const uint4*)(ysrc + (size_t)(st + 2) * kStage + q * 8)
                                          : uint4{0, 0, 0, 0};
       const uint16_t* Bb = Bs + (size_t)buf * kBTN * kRS;
 #pragma unroll
       for (int kk = 0; kk < kStage / 16; ++kk) {
-        bf16x8 af[2], bfr[4];
+        bf16x8 af[2], bfr[2];
 #pragma unroll
         for (int a = 0; a < 2; ++a)
           af[a] = *(const bf16x8*)(Aw + (32 * a + (lane & 31)) * kRS + 16 * kk + 8 * (lane >> 5));
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < 2; ++b)
           bfr[b] = *(const bf16x8*)(Bb + (32 * b + (lane & 31)) * kRS + 16 * kk + 8 * (lane >> 5));
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-          for (int b = 0; b < 4; ++b)
+          for (int b = 0; b < 2; ++b)
             acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
       }
       // clear this wave's nonzeros again (after its own reads, in program order)
@@ -254,7 +256,7 @@ __global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
     // epilogue: moments of this chunk's rows
     if (mine) {
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
+      for (int b = 0; b < 2; ++b) {
         const int col = 32 * b + (lane & 31);
         const int j = j0 + col;
         float sy = 0.f, syy = 0.f, sp = 0.f, spp = 0.f, syp = 0.f;
@@ -276,27 +278,34 @@ __global__ __launch_bounds__(kBThreads, 1) void gather_bf16_kernel(
               }
             }
         }
-        mom[(0 * 4 + b) * kWave + lane] += sy;
-        mom[(1 * 4 + b) * kWave + lane] += syy;
-        mom[(2 * 4 + b) * kWave + lane] += sp;
-        mom[(3 * 4 + b) * kWave + lane] += spp;
-        mom[(4 * 4 + b) * kWave + lane] += syp;
+        M[0][b] += sy;
+        M[1][b] += syy;
+        M[2][b] += sp;
+        M[3][b] += spp;
+        M[4][b] += syp;
       }
     }
   }
-  __syncthreads();
-  // combine the two row halves (waves 2m, 2m+1) and lanes l, l+32 of the same column
-  if (!has || half != 0 || lane >= 32) return;
-  const double* m0 = mom;
-  const double* m1 = mom + 5 * 4 * kWave;
+  // combine lanes l, l+32 (same column, other rows), then the two row halves (waves 2m,
+  // 2m+1) through LDS (the A tiles are no longer needed)
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
+  for (int q = 0; q < 5; ++q)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) M[q][b] += __shfl_xor(M[q][b], 32);
+  __syncthreads();
+  double* red = (double*)As;   // [2 libraries][5][2][32]
+  if (half == 1 && lane < 32)
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) red[(((wave >> 1) * 5 + q) * 2 + b) * 32 + lane] = M[q][b];
+  __syncthreads();
+  if (!has || half != 0 || lane >= 32) return;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
     double S[5];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      const int o = (q * 4 + b) * kWave + lane;
-      S[q] = (m0[o] + m0[o + 32]) + (m1[o] + m1[o + 32]);
-    }
+    for (int q = 0; q < 5; ++q) S[q] = M[q][b] + red[(((wave >> 1) * 5 + q) * 2 + b) * 32 + lane];
     const int j = j0 + 32 * b + lane;
     if (j < n_tgt) {
       const double r = k > 0 ? pearson_from_moments((double)nrows, S[0], S[1], S[2], S[3], S[4])
@@ -318,7 +327,6 @@ extern "C" hipError_t ccm_launch_order(const int* lib_k, int n_lib, int* order, 
 
 extern "C" size_t ccm_bf16_lds_bytes() {
   return 2 * (size_t)ccm::kBTN * ccm::kRS * 2 + 4 * (size_t)ccm::kHalf * ccm::kRS * 2 +
-         4 * 5 * 4 * (size_t)ccm::kWave * sizeof(double) +
          2 * (size_t)ccm::kBRows * ccm::kKMax * 4 + 2 * (size_t)(ccm::kMaxStages + 1) * 4;
 }
 
