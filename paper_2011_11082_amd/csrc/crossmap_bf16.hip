@@ -11,15 +11,15 @@
 // form is bound by MFMA throughput.
 //
 // gfx950 design:
-//   * workgroup = 4 waves = 2 libraries (sorted by E) x one tile of 64 targets; each wave
-//     owns 64 rows of a 128-row chunk of its library against the 64 targets: a 64 x 64
-//     FP32 accumulator (2 x 2 tiles of v_mfma_f32_32x32x16_bf16).  With the FP64 moment
-//     sums in registers the workgroup needs under 80 KB of LDS and 256 registers per lane,
-//     so two workgroups share a CU and one's barriers and latencies overlap the other's
-//     products.
+//   * workgroup = 8 waves = 2 libraries (sorted by E) x one tile of 64 targets; each wave
+//     owns 32 rows of a 128-row chunk of its library against the 64 targets: a 32 x 64
+//     FP32 accumulator (2 tiles of v_mfma_f32_32x32x16_bf16).  With the FP64 moment sums
+//     in registers the workgroup needs under 80 KB of LDS and about 100 VGPRs, so two
+//     workgroups share a CU (four waves per SIMD) and one's barriers and latencies overlap
+//     the other's products.
 //   * K (the neighbour time s) advances in stages of 64: the workgroup stages Y^T[128][64]
 //     BF16 in LDS (double-buffered, loaded two stages ahead through registers) and each wave
-//     scatters the nonzeros of its 64 rows into its own zeroed A tile [64][64]; after its
+//     scatters the nonzeros of its 32 rows into its own zeroed A tile [32][64]; after its
 //     products it writes the same positions back to zero (the tile is private to the
 //     wave, so program order is the only ordering needed).  Every stage runs its products
 //     unconditionally: a branch around them would make the compiler move all 128
@@ -41,12 +41,12 @@ typedef __attribute__((ext_vector_type(16))) float f32x16;
 
 constexpr int kBTN = 64;      // targets per tile
 constexpr int kBRows = 128;   // rows of A per chunk
-constexpr int kHalf = 64;     // rows of A per wave
+constexpr int kHalf = 32;     // rows of A per wave
 constexpr int kStage = 64;    // K per stage
 // LDS row stride of the A and B tiles in BF16 elements: 64 + 8 pad, so the 16 rows read
 // by one 16-lane pass of a 128-bit fragment load start 36 banks apart and never collide
 constexpr int kRS = kStage + 8;
-constexpr int kBThreads = 256;
+constexpr int kBThreads = 512;
 constexpr int kMaxStages = 16384 / kStage;  // L <= 16384
 
 __device__ __forceinline__ uint16_t bf16_bits(float f) {
@@ -134,19 +134,19 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
     const int* __restrict__ stage_off, const int* __restrict__ order, const int* __restrict__ lib_k,
     int n_lib, int nchunk_max, int nst, float* __restrict__ rho, double* __restrict__ moments) {
   extern __shared__ __align__(16) char smem[];
-  // B: two stages of Yt [64 targets][64 s] BF16 (9 KB each); A: per wave [64 rows][64 s]
+  // B: two stages of Yt [64 targets][64 s] BF16 (9 KB each); A: per wave [32 rows][64 s]
   uint16_t* Bs = (uint16_t*)smem;
   uint16_t* As = (uint16_t*)(smem + 2 * kBTN * kRS * 2);
   // the current chunk's sorted entries and stage offsets of both libraries
-  uint32_t* Es = (uint32_t*)(smem + 2 * kBTN * kRS * 2 + 4 * kHalf * kRS * 2);
+  uint32_t* Es = (uint32_t*)(smem + 2 * kBTN * kRS * 2 + 8 * kHalf * kRS * 2);
   int* Ss = (int*)(Es + 2 * kBRows * kKMax);
   const int lane = lane_id();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int half = wave & 1;     // rows 64*half .. 64*half+63 of each 128-row chunk
+  const int half = wave & 3;     // rows 32*half .. 32*half+31 of each 128-row chunk
   // blockIdx.x = library pair (fastest), blockIdx.y = target tile: the workgroups resident
   // at one time share a target tile, whose BF16 and FP32 columns then stay in L2
   const int j0 = blockIdx.y * kBTN;
-  const int li = blockIdx.x * 2 + (wave >> 1);
+  const int li = blockIdx.x * 2 + (wave >> 2);
   const bool has = li < n_lib;
   const int i = has ? __builtin_amdgcn_readfirstlane(order[li]) : 0;
   const int k = has ? __builtin_amdgcn_readfirstlane(lib_k[i]) : 0;
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
   const int lo = k > 0 ? (E - 1) * tau : 0;
   const int nrows = k > 0 ? L - lo : 0;
   const int nchunk = (nrows + kBRows - 1) / kBRows;
-  __shared__ int s_nchunk[4];
+  __shared__ int s_nchunk[8];
   if (lane == 0) s_nchunk[wave] = nchunk;
   uint16_t* Aw = As + (size_t)wave * kHalf * kRS;
   for (int q = lane; q < kHalf * kRS / 2; q += kWave) ((uint32_t*)Aw)[q] = 0u;
@@ -163,45 +163,46 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
 #pragma unroll
   for (int q = 0; q < 5; ++q) M[q][0] = M[q][1] = 0.0;
   __syncthreads();
-  const int nch_all = max(max(s_nchunk[0], s_nchunk[1]), max(s_nchunk[2], s_nchunk[3]));
+  const int nch_all = max(max(max(s_nchunk[0], s_nchunk[1]), max(s_nchunk[2], s_nchunk[3])),
+                          max(max(s_nchunk[4], s_nchunk[5]), max(s_nchunk[6], s_nchunk[7])));
 
-  // B stage loader: thread -> (target row r = tid/4, quarter q = tid%4): 32 bytes
-  const int br = threadIdx.x >> 2;
-  const int bq = threadIdx.x & 3;
-  const uint16_t* ysrc = yt + (size_t)(j0 + br) * Lpad + bq * 16;
+  // B stage loader: thread -> (target row r = tid/8, eighth q = tid%8): 16 bytes
+  const int br = threadIdx.x >> 3;
+  const int bq = threadIdx.x & 7;
+  const uint16_t* ysrc = yt + (size_t)(j0 + br) * Lpad + bq * 8;
   const bool brow_ok = j0 + br < n_tgt;
 
   for (int c = 0; c < nch_all; ++c) {
-    f32x16 acc[2][2];
+    f32x16 acc[1][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 1; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
     const bool mine = c < nchunk;
     // stage this chunk's entries and offsets in LDS (the two waves of a library split the copy)
-    uint32_t* eo = Es + (size_t)(wave >> 1) * kBRows * kKMax;
-    int* so = Ss + (size_t)(wave >> 1) * (kMaxStages + 1);
+    uint32_t* eo = Es + (size_t)(wave >> 2) * kBRows * kKMax;
+    int* so = Ss + (size_t)(wave >> 2) * (kMaxStages + 1);
     __syncthreads();  // previous chunk is done with Es / Ss
     if (mine) {
       const uint32_t* eg = ent + ((size_t)i * nchunk_max + c) * (kBRows * kKMax);
       const int* sg = stage_off + ((size_t)i * nchunk_max + c) * (nst + 1);
       const int ne = sg[nst];
-      for (int q = half * kWave + lane; q <= nst; q += 2 * kWave) so[q] = sg[q];
-      for (int q = half * kWave + lane; q < ne; q += 2 * kWave) eo[q] = eg[q];
+      for (int q = half * kWave + lane; q <= nst; q += 4 * kWave) so[q] = sg[q];
+      for (int q = half * kWave + lane; q < ne; q += 4 * kWave) eo[q] = eg[q];
     }
     // B stages travel through registers two stages ahead of their use
-    uint4 breg[2], breg2[2];
+    uint4 breg[1], breg2[1];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < 1; ++q) {
       breg[q] = brow_ok ? *(const uint4*)(ysrc + q * 8) : uint4{0, 0, 0, 0};
       breg2[q] = (brow_ok && nst > 1) ? *(const uint4*)(ysrc + kStage + q * 8) : uint4{0, 0, 0, 0};
     }
     __syncthreads();  // staged entries visible to both waves of each library
     // one stage; R holds this stage's B rows and is reloaded with stage st + 2 once stored,
     // so the two register sets alternate without copies
-    auto stage = [&](int st, uint4 (&R)[2]) {
+    auto stage = [&](int st, uint4 (&R)[1]) {
       const int buf = st & 1;
       // scatter this wave's nonzeros of the stage (rows of its half only)
       int e0 = 0, e1 = 0;
@@ -212,30 +213,29 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
       for (int e = e0 + lane; e < e1; e += kWave) {
         const uint32_t v = eo[e];
         const int row = v & 127;
-        if ((row >> 6) == half) Aw[(row & 63) * kRS + ((v >> 7) & 63)] = (uint16_t)(v >> 16);
+        if ((row >> 5) == half) Aw[(row & 31) * kRS + ((v >> 7) & 63)] = (uint16_t)(v >> 16);
       }
       {
-        uint16_t* dst = Bs + (size_t)buf * kBTN * kRS + br * kRS + bq * 16;
-#pragma unroll
-        for (int q = 0; q < 2; ++q) *(uint4*)(dst + q * 8) = R[q];
+        uint16_t* dst = Bs + (size_t)buf * kBTN * kRS + br * kRS + bq * 8;
+        *(uint4*)dst = R[0];
       }
       __syncthreads();  // B stage `buf` complete; the other buffer is free
 #pragma unroll
-      for (int q = 0; q < 2; ++q)
+      for (int q = 0; q < 1; ++q)
         R[q] = (brow_ok && st + 2 < nst) ? *(const uint4*)(ysrc + (size_t)(st + 2) * kStage + q * 8)
                                          : uint4{0, 0, 0, 0};
       const uint16_t* Bb = Bs + (size_t)buf * kBTN * kRS;
 #pragma unroll
       for (int kk = 0; kk < kStage / 16; ++kk) {
-        bf16x8 af[2], bfr[2];
+        bf16x8 af[1], bfr[2];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 1; ++a)
           af[a] = *(const bf16x8*)(Aw + (32 * a + (lane & 31)) * kRS + 16 * kk + 8 * (lane >> 5));
 #pragma unroll
         for (int b = 0; b < 2; ++b)
           bfr[b] = *(const bf16x8*)(Bb + (32 * b + (lane & 31)) * kRS + 16 * kk + 8 * (lane >> 5));
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 1; ++a)
 #pragma unroll
           for (int b = 0; b < 2; ++b)
             acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
       for (int e = e0 + lane; e < e1; e += kWave) {
         const uint32_t v = eo[e];
         const int row = v & 127;
-        if ((row >> 6) == half) Aw[(row & 63) * kRS + ((v >> 7) & 63)] = 0;
+        if ((row >> 5) == half) Aw[(row & 31) * kRS + ((v >> 7) & 63)] = 0;
       }
     };
     int st = 0;
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
         float sy = 0.f, syy = 0.f, sp = 0.f, spp = 0.f, syp = 0.f;
         if (j < n_tgt) {
 #pragma unroll
-          for (int a = 0; a < 2; ++a)
+          for (int a = 0; a < 1; ++a)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
               const int row = kHalf * half + 32 * a + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -293,19 +293,23 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
 #pragma unroll
     for (int b = 0; b < 2; ++b) M[q][b] += __shfl_xor(M[q][b], 32);
   __syncthreads();
-  double* red = (double*)As;   // [2 libraries][5][2][32]
-  if (half == 1 && lane < 32)
+  double* red = (double*)As;   // [2 libraries][3 parts][5][2][32]
+  if (half >= 1 && lane < 32)
 #pragma unroll
     for (int q = 0; q < 5; ++q)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) red[(((wave >> 1) * 5 + q) * 2 + b) * 32 + lane] = M[q][b];
+      for (int b = 0; b < 2; ++b)
+        red[((((wave >> 2) * 3 + half - 1) * 5 + q) * 2 + b) * 32 + lane] = M[q][b];
   __syncthreads();
   if (!has || half != 0 || lane >= 32) return;
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     double S[5];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) S[q] = M[q][b] + red[(((wave >> 1) * 5 + q) * 2 + b) * 32 + lane];
+    for (int q = 0; q < 5; ++q) {
+      S[q] = M[q][b];
+      for (int h = 0; h < 3; ++h) S[q] += red[((((wave >> 2) * 3 + h) * 5 + q) * 2 + b) * 32 + lane];
+    }
     const int j = j0 + 32 * b + lane;
     if (j < n_tgt) {
       const double r = k > 0 ? pearson_from_moments((double)nrows, S[0], S[1], S[2], S[3], S[4])
@@ -326,7 +330,7 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
 extern "C" hipError_t ccm_launch_order(const int* lib_k, int n_lib, int* order, hipStream_t stream);
 
 extern "C" size_t ccm_bf16_lds_bytes() {
-  return 2 * (size_t)ccm::kBTN * ccm::kRS * 2 + 4 * (size_t)ccm::kHalf * ccm::kRS * 2 +
+  return 2 * (size_t)ccm::kBTN * ccm::kRS * 2 + 8 * (size_t)ccm::kHalf * ccm::kRS * 2 +
          2 * (size_t)ccm::kBRows * ccm::kKMax * 4 + 2 * (size_t)(ccm::kMaxStages + 1) * 4;
 }
 
