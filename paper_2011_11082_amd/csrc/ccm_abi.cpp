@@ -99,8 +99,8 @@ TargetEWs target_E_ws(int L, int n_tab, int n_tgt, int k_max) {
   return w;
 }
 
-// Workspace of the BF16 cross-map: BF16 target panel (target-major), stage-sorted table
-// entries, stage offsets, lib_k, order.
+// Workspace of the BF16 cross-map: BF16 target panel (target-major), table entries sorted
+// by (stage, row quarter), their bucket offsets, lib_k, order.
 struct Bf16Ws {
   size_t off_yt, off_ent, off_so, off_libk, off_order, total;
 };
@@ -112,7 +112,7 @@ Bf16Ws bf16_ws(int L, int n_lib, int n_tgt) {
   w.off_yt = 0;
   w.off_ent = align_up(w.off_yt + (size_t)n_tgt * nst * 64 * 2);
   w.off_so = align_up(w.off_ent + (size_t)n_lib * nch * 128 * CCM_K_MAX * 4);
-  w.off_libk = align_up(w.off_so + (size_t)n_lib * nch * (nst + 1) * 4);
+  w.off_libk = align_up(w.off_so + (size_t)n_lib * nch * (4 * nst + 1) * 4);
   w.off_order = align_up(w.off_libk + (size_t)n_lib * 4);
   w.total = align_up(w.off_order + (size_t)n_lib * 4);
   return w;

@@ -26,8 +26,11 @@
 //     accumulators between AGPRs and VGPRs at every stage.
 //   * The stage loop is unrolled by two so the two B register sets alternate roles (each
 //     is stored to LDS, then reloaded two stages ahead) without register copies.
-//   * Table entries are pre-sorted per (library, 128-row chunk) by stage and packed into
-//     32 bits (row, column within stage, BF16 weight).
+//   * Table entries are pre-sorted per (library, 128-row chunk) by (stage, row quarter) and
+//     packed into 32 bits (row, column within stage, BF16 weight), so each wave scatters and
+//     clears only its own entries; their bucket offsets are wave-uniform loads.
+//   * The epilogue reads the observed FP32 y of a wave's rows at uniform strides from one
+//     pointer per lane (one branch-free pass for every chunk that lies inside the series).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -74,14 +77,15 @@ __global__ __launch_bounds__(256) void transpose_bf16_kernel(const float* __rest
   }
 }
 
-// Per (chunk, library): sort the chunk's table entries by stage.  Entry = row (7 bits) |
-// column within stage (6 bits) << 7 | BF16 weight << 16.  Offsets [nst + 1] per chunk.
+// Per (chunk, library): sort the chunk's table entries by (stage, row quarter), quarter =
+// row / 32 (the rows of one wave).  Entry = row (7 bits) | column within stage (6 bits) << 7
+// | BF16 weight << 16.  Offsets [4 nst + 1] per chunk.
 __global__ __launch_bounds__(kBRows) void bf16_entries_kernel(
     const int* __restrict__ nbr_idx, const float* __restrict__ nbr_w, const int* __restrict__ lib_E,
     int L, int k_max, int tau, int nchunk_max, int nst, uint32_t* __restrict__ ent,
     int* __restrict__ stage_off, int* __restrict__ lib_k) {
-  __shared__ int cnt[kMaxStages];
-  __shared__ int cur[kMaxStages];
+  __shared__ int cnt[4 * kMaxStages];
+  __shared__ int cur[4 * kMaxStages];
   const int c = blockIdx.x;
   const int i = blockIdx.y;
   const int E = lib_E[i];
@@ -90,7 +94,8 @@ __global__ __launch_bounds__(kBRows) void bf16_entries_kernel(
   bool libok = E >= 1 && E <= kEMax && k <= k_max && (L - lo) >= k + 1;
   if (libok) libok = nbr_idx[((size_t)i * L + lo) * k_max] >= 0;
   if (c == 0 && threadIdx.x == 0) lib_k[i] = libok ? k : 0;
-  for (int q = threadIdx.x; q < nst; q += blockDim.x) cnt[q] = 0;
+  const int nb = 4 * nst;
+  for (int q = threadIdx.x; q < nb; q += blockDim.x) cnt[q] = 0;
   __syncthreads();
   const int row = threadIdx.x;
   const int t = lo + c * kBRows + row;
@@ -102,26 +107,26 @@ __global__ __launch_bounds__(kBRows) void bf16_entries_kernel(
       const int v = nbr_idx[((size_t)i * L + t) * k_max + m];
       sidx[m] = (v >= 0 && v < L) ? v : -1;
       wv[m] = nbr_w[((size_t)i * L + t) * k_max + m];
-      if (sidx[m] >= 0) atomicAdd(&cnt[sidx[m] / kStage], 1);
+      if (sidx[m] >= 0) atomicAdd(&cnt[4 * (sidx[m] / kStage) + (row >> 5)], 1);
     }
   }
   __syncthreads();
-  int* so = stage_off + ((size_t)i * nchunk_max + c) * (nst + 1);
+  int* so = stage_off + ((size_t)i * nchunk_max + c) * (nb + 1);
   if (threadIdx.x == 0) {
     int p = 0;
-    for (int q = 0; q < nst; ++q) {
+    for (int q = 0; q < nb; ++q) {
       cur[q] = p;
       so[q] = p;
       p += cnt[q];
     }
-    so[nst] = p;
+    so[nb] = p;
   }
   __syncthreads();
   uint32_t* eo = ent + ((size_t)i * nchunk_max + c) * (kBRows * kKMax);
   if (rowok)
     for (int m = 0; m < k; ++m)
       if (sidx[m] >= 0) {
-        const int q = sidx[m] / kStage;
+        const int q = 4 * (sidx[m] / kStage) + (row >> 5);
         const int p = atomicAdd(&cur[q], 1);
         eo[p] = (uint32_t)row | ((uint32_t)(sidx[m] % kStage) << 7) |
                 ((uint32_t)bf16_bits(wv[m]) << 16);
@@ -137,9 +142,8 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
   // B: two stages of Yt [64 targets][64 s] BF16 (9 KB each); A: per wave [32 rows][64 s]
   uint16_t* Bs = (uint16_t*)smem;
   uint16_t* As = (uint16_t*)(smem + 2 * kBTN * kRS * 2);
-  // the current chunk's sorted entries and stage offsets of both libraries
+  // the current chunk's sorted entries of both libraries
   uint32_t* Es = (uint32_t*)(smem + 2 * kBTN * kRS * 2 + 8 * kHalf * kRS * 2);
-  int* Ss = (int*)(Es + 2 * kBRows * kKMax);
   const int lane = lane_id();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int half = wave & 3;     // rows 32*half .. 32*half+31 of each 128-row chunk
@@ -181,15 +185,14 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
     const bool mine = c < nchunk;
-    // stage this chunk's entries and offsets in LDS (the two waves of a library split the copy)
+    // stage this chunk's entries in LDS (the four waves of a library split the copy); the
+    // bucket offsets of this wave's quarter are read as uniform values from memory
     uint32_t* eo = Es + (size_t)(wave >> 2) * kBRows * kKMax;
-    int* so = Ss + (size_t)(wave >> 2) * (kMaxStages + 1);
-    __syncthreads();  // previous chunk is done with Es / Ss
+    const int* sg = stage_off + ((size_t)i * nchunk_max + c) * (4 * nst + 1) + half;
+    __syncthreads();  // previous chunk is done with Es
     if (mine) {
       const uint32_t* eg = ent + ((size_t)i * nchunk_max + c) * (kBRows * kKMax);
-      const int* sg = stage_off + ((size_t)i * nchunk_max + c) * (nst + 1);
-      const int ne = sg[nst];
-      for (int q = half * kWave + lane; q <= nst; q += 4 * kWave) so[q] = sg[q];
+      const int ne = sg[4 * nst - half];
       for (int q = half * kWave + lane; q < ne; q += 4 * kWave) eo[q] = eg[q];
     }
     // B stages travel through registers two stages ahead of their use
@@ -204,16 +207,15 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
     // so the two register sets alternate without copies
     auto stage = [&](int st, uint4 (&R)[1]) {
       const int buf = st & 1;
-      // scatter this wave's nonzeros of the stage (rows of its half only)
+      // scatter this wave's nonzeros of the stage (its own bucket)
       int e0 = 0, e1 = 0;
       if (mine) {
-        e0 = so[st];
-        e1 = so[st + 1];
+        e0 = sg[4 * st];
+        e1 = sg[4 * st + 1];
       }
       for (int e = e0 + lane; e < e1; e += kWave) {
         const uint32_t v = eo[e];
-        const int row = v & 127;
-        if ((row >> 5) == half) Aw[(row & 31) * kRS + ((v >> 7) & 63)] = (uint16_t)(v >> 16);
+        Aw[(v & 31) * kRS + ((v >> 7) & 63)] = (uint16_t)(v >> 16);
       }
       {
         uint16_t* dst = Bs + (size_t)buf * kBTN * kRS + br * kRS + bq * 8;
@@ -241,11 +243,7 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
             acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
       }
       // clear this wave's nonzeros again (after its own reads, in program order)
-      for (int e = e0 + lane; e < e1; e += kWave) {
-        const uint32_t v = eo[e];
-        const int row = v & 127;
-        if ((row >> 5) == half) Aw[(row & 31) * kRS + ((v >> 7) & 63)] = 0;
-      }
+      for (int e = e0 + lane; e < e1; e += kWave) Aw[(eo[e] & 31) * kRS + ((eo[e] >> 7) & 63)] = 0;
     };
     int st = 0;
     for (; st + 1 < nst; st += 2) {
@@ -255,21 +253,33 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
     if (st < nst) stage(st, breg);
     // epilogue: moments of this chunk's rows
     if (mine) {
+      // accumulator element r of lane l holds row 8 (r / 4) + 4 (l / 32) + r % 4 of the
+      // wave's 32; the observed y of those rows are read at uniform strides from one pointer
+      const int trow = lo + c * kBRows + kHalf * half + 4 * (lane >> 5);
+      const bool full = lo + c * kBRows + kHalf * half + kHalf <= L;   // uniform
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        const int col = 32 * b + (lane & 31);
-        const int j = j0 + col;
+        const int j = j0 + 32 * b + (lane & 31);
         float sy = 0.f, syy = 0.f, sp = 0.f, spp = 0.f, syp = 0.f;
         if (j < n_tgt) {
-#pragma unroll
-          for (int a = 0; a < 1; ++a)
+          const float* yb = ts + (int64_t)trow * ld + tgt0 + j;
+          if (full) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-              const int row = kHalf * half + 32 * a + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-              const int t = lo + c * kBRows + row;
-              if (t < L) {
-                const float y = ts[(int64_t)t * ld + tgt0 + j];
-                const float p = acc[a][b][r];
+              const float y = yb[(int64_t)(8 * (r >> 2) + (r & 3)) * ld];
+              const float p = acc[0][b][r];
+              sy += y;
+              syy = fmaf(y, y, syy);
+              sp += p;
+              spp = fmaf(p, p, spp);
+              syp = fmaf(y, p, syp);
+            }
+          } else {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              if (trow + 8 * (r >> 2) + (r & 3) < L) {
+                const float y = yb[(int64_t)(8 * (r >> 2) + (r & 3)) * ld];
+                const float p = acc[0][b][r];
                 sy += y;
                 syy = fmaf(y, y, syy);
                 sp += p;
@@ -277,6 +287,7 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
                 syp = fmaf(y, p, syp);
               }
             }
+          }
         }
         M[0][b] += sy;
         M[1][b] += syy;
@@ -331,7 +342,7 @@ extern "C" hipError_t ccm_launch_order(const int* lib_k, int n_lib, int* order, 
 
 extern "C" size_t ccm_bf16_lds_bytes() {
   return 2 * (size_t)ccm::kBTN * ccm::kRS * 2 + 8 * (size_t)ccm::kHalf * ccm::kRS * 2 +
-         2 * (size_t)ccm::kBRows * ccm::kKMax * 4 + 2 * (size_t)(ccm::kMaxStages + 1) * 4;
+         2 * (size_t)ccm::kBRows * ccm::kKMax * 4;
 }
 
 extern "C" hipError_t ccm_launch_crossmap_bf16(const float* ts, int64_t ld, int L, int tau, int tgt0,
