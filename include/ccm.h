@@ -202,7 +202,8 @@ ccm_status ccm_crossmap_rho_target_E(const float* ts, int64_t ld, int32_t L,
  *   The gradient through a zero distance (d_k = 0 or d_1 = 0) is taken as 0.  Pairs whose
  *   rho is NaN contribute nothing.  Accumulation order is fixed (no atomics), so results
  *   are deterministic.
- *   The tables' rows must hold distinct neighbours (as ccm_knn writes them).
+ *   The tables' rows must hold distinct neighbours (as ccm_knn writes them).  Padding entries
+ *   (index -1, as in rows of a subsampled table) count as absent: no weight, no distance.
  * Errors: EINVAL, ERANGE, EWORKSPACE.  Workspace: ccm_workspace_size(CCM_OP_CROSSMAP_BACKWARD,
  * L, n_lib, n_pairs, k_max).
  */

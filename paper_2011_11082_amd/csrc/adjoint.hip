@@ -16,14 +16,19 @@
 //            dL/dx(t - e tau) += coef (x(t-e tau) - x(n_m - e tau))
 //            dL/dx(n_m - e tau) -= coef (x(t-e tau) - x(n_m - e tau))
 //
-// gfx950 design: no atomics, fixed summation order (deterministic results).  Kernel 1:
-// one workgroup per pair recomputes yhat and the FP64 Pearson pieces and stores H, Gy.
-// Kernel 2: one thread per (pair, t) turns wbar into distance coefficients (distances
-// recomputed in FP64 from the library series).  Kernel 3: one workgroup per library builds
-// the transposed neighbour relation (for each time s, the table entries whose neighbour is
-// s, in table order).  Kernel 4: one thread per (pair, s) gathers everything that lands on
-// time s from those lists, O(E k) per (pair, s).  Kernel 5: one thread per s adds the
-// pairs' contributions in pair order into the target and library gradients.
+// gfx950 design: no atomics, fixed summation order (deterministic results).
+//   Kernel 3 (first): one workgroup per library builds the transposed neighbour relation
+//   (for each time s, the table entries whose neighbour is s, in table order), the position
+//   of every entry in it, the weights in that order, and an m-major copy of the table.
+//   Kernel 1: one workgroup per pair recomputes yhat and the FP64 Pearson pieces and stores
+//   H, Gy.  Kernel 2: one thread per (pair, t) turns wbar into distance coefficients
+//   (distances recomputed in FP64 from the library series), written m-major and in the
+//   transposed order.  Kernel 4: one thread per (pair, s) gathers everything that lands on
+//   time s, O(E k) per (pair, s): the query side reads m-major rows (consecutive s in
+//   consecutive lanes), the neighbour side reads the transposed lists, whose coefficients
+//   and weights are contiguous.  Kernel 5: one wave per (64 times, column hash) adds the
+//   pairs' contributions in pair order into the target and library gradients.
+// Padding entries (-1) count as absent everywhere.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -76,7 +81,8 @@ __global__ __launch_bounds__(kBwThreads) void bw_pair_kernel(
     if (t >= lo) {
       const int* ri = nbr_idx + ((size_t)i * L + t) * k_max;
       const float* rw = nbr_w + ((size_t)i * L + t) * k_max;
-      for (int m = 0; m < k; ++m) v = fmaf(rw[m], ts[(int64_t)ri[m] * ld + j], v);
+      for (int m = 0; m < k; ++m)
+        if (ri[m] >= 0) v = fmaf(rw[m], ts[(int64_t)ri[m] * ld + j], v);   // -1: padding
       sy += ts[(int64_t)t * ld + j];
       sp += v;
     }
@@ -118,32 +124,46 @@ __global__ __launch_bounds__(kBwThreads) void bw_pair_kernel(
   if (threadIdx.x == 0) pair_ok[p] = good ? 1 : 0;
 }
 
-// coef[p][t][m] = dbar_m / d_m (0 for zero distances), one thread per (pair, t).
+// coef = dbar_m / d_m (0 for zero distances), one thread per (pair, t), written twice: m-major
+// (com[p][m][t], read by the query side) and in the library's transposed order (coT[p][q] at
+// q = pos[t][m], read by the neighbour side).
 __global__ __launch_bounds__(256) void bw_coef_kernel(
     const float* __restrict__ ts, int64_t ld, int L, const float* __restrict__ lib_ts,
     const int* __restrict__ nbr_idx, const int* __restrict__ lib_E, int k_max, int tau,
     const int* __restrict__ pair_lib, const int* __restrict__ pair_tgt, int n_pairs,
-    const float* __restrict__ H, const int* __restrict__ pair_ok, float* __restrict__ coef) {
+    const float* __restrict__ H, const int* __restrict__ pair_ok, const int* __restrict__ csr_pos,
+    float* __restrict__ com, float* __restrict__ coT) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= (int64_t)n_pairs * L) return;
   const int p = (int)(g / L);
   const int t = (int)(g % L);
-  float* co = coef + ((size_t)p * L + t) * k_max;
+  float* cm_out = com + (size_t)p * k_max * L + t;     // stride L between m
   const int i = pair_lib[p];
   const int E = pair_ok[p] ? lib_E[i] : 0;
   const int k = E + 1;
   const int lo = (E - 1) * tau;
   if (!pair_ok[p] || t < lo) {
-    for (int m = 0; m < k_max; ++m) co[m] = 0.0f;
+    for (int m = 0; m < k_max; ++m) cm_out[(size_t)m * L] = 0.0f;
     return;
   }
+  const int* pos = csr_pos + ((size_t)i * L + t) * k_max;
+  float* cT = coT + (size_t)p * L * k_max;
   const int j = pair_tgt[p];
   const float* x = lib_ts + (size_t)i * L;
   const int* ri = nbr_idx + ((size_t)i * L + t) * k_max;
   const double h = H[(size_t)p * L + t];
   double d[kKMax], u[kKMax], wb[kKMax];
+  if (ri[0] < 0) {   // a row of padding only (a subsampled table): no contribution
+    for (int m = 0; m < k_max; ++m) cm_out[(size_t)m * L] = 0.0f;
+    return;
+  }
   for (int m = 0; m < k; ++m) {
     const int nb = ri[m];
+    if (nb < 0) {   // padding entry: weight 0, no distance
+      d[m] = INFINITY;
+      wb[m] = 0.0;
+      continue;
+    }
     double dd = 0.0;
     for (int e = 0; e < E; ++e) {
       const double df = (double)x[t - e * tau] - (double)x[nb - e * tau];
@@ -155,7 +175,7 @@ __global__ __launch_bounds__(256) void bw_coef_kernel(
   const double d1 = d[0];
   double S = 0.0;
   for (int m = 0; m < k; ++m) {
-    u[m] = d1 > 0.0 ? exp(-d[m] / d1) : (d[m] == 0.0 ? 1.0 : 0.0);
+    u[m] = ri[m] < 0 ? 0.0 : d1 > 0.0 ? exp(-d[m] / d1) : (d[m] == 0.0 ? 1.0 : 0.0);
     S += u[m];
   }
   double sw = 0.0;
@@ -163,15 +183,20 @@ __global__ __launch_bounds__(256) void bw_coef_kernel(
   double dbar1 = 0.0;
   for (int m = 0; m < k_max; ++m) {
     double cm = 0.0;
-    if (m >= 1 && m < k && d1 > 0.0 && d[m] > 0.0) {
+    if (m >= 1 && m < k && ri[m] >= 0 && d1 > 0.0 && d[m] > 0.0) {
       const double ub = (wb[m] - sw) / S;
       const double db = -ub * u[m] / d1;
       dbar1 += ub * u[m] * d[m] / (d1 * d1);
       cm = db / d[m];
     }
-    if (m >= 1) co[m] = (float)cm;
+    if (m >= 1) {
+      cm_out[(size_t)m * L] = (float)cm;
+      if (m < k && ri[m] >= 0 && ri[m] < L) cT[pos[m]] = (float)cm;
+    }
   }
-  co[0] = d1 > 0.0 ? (float)(dbar1 / d1) : 0.0f;
+  const float c0 = d1 > 0.0 ? (float)(dbar1 / d1) : 0.0f;
+  cm_out[0] = c0;
+  if (ri[0] >= 0 && ri[0] < L) cT[pos[0]] = c0;
 }
 
 // Contributions of pair p to time s: target (tc) and library (lc).  One thread per (p, s).
@@ -182,8 +207,9 @@ __global__ __launch_bounds__(256) void bw_coef_kernel(
 constexpr int kTrThreads = 256;
 
 __global__ __launch_bounds__(kTrThreads) void bw_transpose_kernel(
-    const int* __restrict__ nbr_idx, const int* __restrict__ lib_E, int L, int k_max, int tau,
-    int* __restrict__ csr_off, int* __restrict__ csr_ent) {
+    const int* __restrict__ nbr_idx, const float* __restrict__ nbr_w, const int* __restrict__ lib_E,
+    int L, int k_max, int tau, int* __restrict__ csr_off, int* __restrict__ csr_ent,
+    int* __restrict__ csr_pos, float* __restrict__ csr_w, int* __restrict__ idx_m) {
   extern __shared__ int cnt[];          // [L + 1], then chunk sums [kTrThreads]
   int* csum = cnt + L + 1;
   const int i = blockIdx.x;
@@ -194,9 +220,11 @@ __global__ __launch_bounds__(kTrThreads) void bw_transpose_kernel(
   for (int q = threadIdx.x; q <= L; q += blockDim.x) cnt[q] = 0;
   __syncthreads();
   const int* tab = nbr_idx + (size_t)i * L * k_max;
+  int* im = idx_m + (size_t)i * k_max * L;
   for (int q = threadIdx.x; q < (L - lo) * k; q += blockDim.x) {
     const int t = lo + q / k, m = q % k;
     const int s = tab[(size_t)t * k_max + m];
+    im[(size_t)m * L + t] = s;
     if (s >= 0 && s < L) atomicAdd(&cnt[s], 1);
   }
   __syncthreads();
@@ -227,22 +255,30 @@ __global__ __launch_bounds__(kTrThreads) void bw_transpose_kernel(
   for (int q = threadIdx.x; q <= L; q += blockDim.x) off[q] = cnt[q];
   __syncthreads();
   int* ent = csr_ent + (size_t)i * L * k_max;
+  int* pos = csr_pos + (size_t)i * L * k_max;
+  float* cw = csr_w + (size_t)i * L * k_max;
+  const float* wtab = nbr_w + (size_t)i * L * k_max;
   if (threadIdx.x < kWave) {
     const int lane = threadIdx.x;
     for (int t = lo; t < L; ++t) {
       const int s = lane < k ? tab[(size_t)t * k_max + lane] : -1;
-      if (s >= 0 && s < L) ent[cnt[s]++] = t * 32 + lane;
+      if (s >= 0 && s < L) {
+        const int q = cnt[s]++;
+        ent[q] = t * 32 + lane;
+        pos[(size_t)t * k_max + lane] = q;
+        cw[q] = wtab[(size_t)t * k_max + lane];
+      }
     }
   }
 }
 
 __global__ __launch_bounds__(256) void bw_scatter_kernel(
     const float* __restrict__ ts, int64_t ld, int L, const float* __restrict__ lib_ts,
-    const int* __restrict__ nbr_idx, const float* __restrict__ nbr_w, const int* __restrict__ lib_E,
-    int k_max, int tau, const int* __restrict__ pair_lib, int n_pairs, const float* __restrict__ H,
-    const float* __restrict__ Gy, const int* __restrict__ pair_ok, const float* __restrict__ coef,
-    const int* __restrict__ csr_off, const int* __restrict__ csr_ent, float* __restrict__ tc,
-    float* __restrict__ lc) {
+    const int* __restrict__ lib_E, int k_max, int tau, const int* __restrict__ pair_lib,
+    int n_pairs, const float* __restrict__ H, const float* __restrict__ Gy,
+    const int* __restrict__ pair_ok, const float* __restrict__ com, const float* __restrict__ coT,
+    const int* __restrict__ csr_off, const int* __restrict__ csr_ent, const float* __restrict__ csr_w,
+    const int* __restrict__ idx_m, float* __restrict__ tc, float* __restrict__ lc) {
   const int p = blockIdx.y;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= L) return;
@@ -259,10 +295,12 @@ __global__ __launch_bounds__(256) void bw_scatter_kernel(
   const int lo = (E - 1) * tau;
   const float* x = lib_ts + (size_t)i * L;
   const float* hp = H + (size_t)p * L;
-  const float* co = coef + (size_t)p * L * k_max;
+  const float* cm = com + (size_t)p * k_max * L;       // [m][t]
+  const float* cT = coT + (size_t)p * L * k_max;       // transposed order
+  const int* im = idx_m + (size_t)i * k_max * L;       // [m][t]
   const int* off = csr_off + (size_t)i * (L + 1);
   const int* ent = csr_ent + (size_t)i * L * k_max;
-  const float* wrow = nbr_w + (size_t)i * L * k_max;
+  const float* cw = csr_w + (size_t)i * L * k_max;
   const double xs = x[s];
   double T = s >= lo ? (double)Gy[(size_t)p * L + s] : 0.0;
   double Lb = 0.0;
@@ -270,8 +308,10 @@ __global__ __launch_bounds__(256) void bw_scatter_kernel(
   for (int e = 0; e < E; ++e) {
     const int t = s + e * tau;
     if (t < lo || t >= L) continue;
-    const int* ri = nbr_idx + ((size_t)i * L + t) * k_max;
-    for (int m = 0; m < k; ++m) Lb += (double)co[(size_t)t * k_max + m] * (xs - (double)x[ri[m] - e * tau]);
+    for (int m = 0; m < k; ++m) {
+      const int n = im[(size_t)m * L + t];
+      if (n >= 0) Lb += (double)cm[(size_t)m * L + t] * (xs - (double)x[n - e * tau]);
+    }
   }
   // s as a neighbour (the looked-up target value; lag 0 of the neighbour's point) and as
   // lag coordinate e >= 1 of a neighbour n = s + e tau: the transposed lists of s + e tau
@@ -282,26 +322,49 @@ __global__ __launch_bounds__(256) void bw_scatter_kernel(
       const int v = ent[q];
       const int t = v >> 5, m = v & 31;
       if (t < lo || t >= L || m >= k) continue;   // only a malformed table (repeated neighbours)
-      if (e == 0) T += (double)wrow[(size_t)t * k_max + m] * (double)hp[t];
-      Lb -= (double)co[(size_t)t * k_max + m] * ((double)x[t - e * tau] - xs);
+      if (e == 0) T += (double)cw[q] * (double)hp[t];
+      Lb -= (double)cT[q] * ((double)x[t - e * tau] - xs);
     }
   }
   tco[s] = (float)T;
   lco[s] = (float)Lb;
 }
 
-// grad_ts[s][tgt_p] += tc[p][s], grad_lib[lib_p][s] += lc[p][s], pairs in order.
-__global__ void bw_reduce_kernel(int64_t ld, int L, const int* __restrict__ pair_lib,
-                                 const int* __restrict__ pair_tgt, int n_pairs,
-                                 const int* __restrict__ pair_ok, const float* __restrict__ tc,
-                                 const float* __restrict__ lc, float* __restrict__ grad_ts,
-                                 float* __restrict__ grad_lib) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= L) return;
-  for (int p = 0; p < n_pairs; ++p) {
-    if (!pair_ok[p]) continue;
-    if (grad_ts) grad_ts[(int64_t)s * ld + pair_tgt[p]] += tc[(size_t)p * L + s];
-    if (grad_lib) grad_lib[(size_t)pair_lib[p] * L + s] += lc[(size_t)p * L + s];
+// grad_ts[s][tgt_p] += tc[p][s], grad_lib[lib_p][s] += lc[p][s], pairs in order.  One wave
+// per (64 consecutive s, hash h): it takes the pairs whose target (for grad_ts) or library
+// (for grad_lib) is congruent to h modulo kRedHash, in pair order, so every output element
+// is summed by one lane in pair order.  The pair list is read 64 entries at a time.
+constexpr int kRedHash = 64;
+
+__global__ __launch_bounds__(kWave) void bw_reduce_kernel(
+    int64_t ld, int L, const int* __restrict__ pair_lib, const int* __restrict__ pair_tgt,
+    int n_pairs, const int* __restrict__ pair_ok, const float* __restrict__ tc,
+    const float* __restrict__ lc, float* __restrict__ grad_ts, float* __restrict__ grad_lib) {
+  const int lane = lane_id();
+  const int s = blockIdx.x * kWave + lane;
+  const int h = blockIdx.y;
+  const bool in = s < L;
+  for (int p0 = 0; p0 < n_pairs; p0 += kWave) {
+    const int pc = p0 + lane;
+    const bool okp = pc < n_pairs && pair_ok[pc] != 0;
+    const int tg = okp ? pair_tgt[pc] : -1;
+    const int lb = okp ? pair_lib[pc] : -1;
+    uint64_t mt = grad_ts ? ballot(okp && tg % kRedHash == h) : 0;
+    uint64_t ml = grad_lib ? ballot(okp && lb % kRedHash == h) : 0;
+    uint64_t mall = mt | ml;
+    while (mall) {
+      const int b = __builtin_ctzll(mall);
+      mall &= mall - 1;
+      const int p = p0 + b;
+      if ((mt >> b) & 1) {
+        const int j = readlane(tg, b);
+        if (in) grad_ts[(int64_t)s * ld + j] += tc[(size_t)p * L + s];
+      }
+      if ((ml >> b) & 1) {
+        const int i = readlane(lb, b);
+        if (in) grad_lib[(size_t)i * L + s] += lc[(size_t)p * L + s];
+      }
+    }
   }
 }
 
@@ -310,11 +373,13 @@ __global__ void bw_reduce_kernel(int64_t ld, int L, const int* __restrict__ pair
 static size_t up256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 extern "C" size_t ccm_backward_ws_bytes(int L, int n_lib, int n_pairs, int k_max) {
-  // yhat, H, Gy, tc, lc: [P][L] floats; coef: [P][L][k_max] floats; pair_ok: [P] ints;
-  // transposed tables: offsets [n_lib][L + 1], entries [n_lib][L][k_max] ints
+  // yhat, H, Gy, tc, lc: [P][L] floats; coefficients twice: [P][k_max][L] and [P][L k_max]
+  // floats; pair_ok: [P] ints; per library: CSR offsets [L + 1], entries, positions, weights
+  // and the m-major table copy, [L k_max] each
   const size_t a = up256((size_t)n_pairs * L * 4);
-  return 5 * a + up256((size_t)n_pairs * L * k_max * 4) + up256((size_t)n_pairs * 4) +
-         up256((size_t)n_lib * (L + 1) * 4) + up256((size_t)n_lib * L * k_max * 4);
+  const size_t c = up256((size_t)n_pairs * L * k_max * 4);
+  const size_t t = up256((size_t)n_lib * L * k_max * 4);
+  return 5 * a + 2 * c + up256((size_t)n_pairs * 4) + up256((size_t)n_lib * (L + 1) * 4) + 4 * t;
 }
 
 extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, const float* lib_ts,
@@ -331,11 +396,17 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
   float* Gy = (float*)(base + 2 * a);
   float* tc = (float*)(base + 3 * a);
   float* lc = (float*)(base + 4 * a);
-  float* coef = (float*)(base + 5 * a);
-  char* after_coef = base + 5 * a + up256((size_t)n_pairs * L * k_max * 4);
+  const size_t c = up256((size_t)n_pairs * L * k_max * 4);
+  const size_t tb = up256((size_t)n_lib * L * k_max * 4);
+  float* com = (float*)(base + 5 * a);
+  float* coT = (float*)(base + 5 * a + c);
+  char* after_coef = base + 5 * a + 2 * c;
   int* pair_ok = (int*)after_coef;
   int* csr_off = (int*)(after_coef + up256((size_t)n_pairs * 4));
   int* csr_ent = (int*)((char*)csr_off + up256((size_t)n_lib * (L + 1) * 4));
+  int* csr_pos = (int*)((char*)csr_ent + tb);
+  float* csr_w = (float*)((char*)csr_pos + tb);
+  int* idx_m = (int*)((char*)csr_w + tb);
   static bool attr = false;
   if (!attr) {
     hipFuncAttributes fa;
@@ -348,19 +419,20 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
     attr = true;
   }
   hipLaunchKernelGGL(ccm::bw_transpose_kernel, dim3(n_lib), dim3(ccm::kTrThreads),
-                     (size_t)(L + 1 + ccm::kTrThreads) * sizeof(int), stream, nbr_idx, lib_E, L,
-                     k_max, tau, csr_off, csr_ent);
+                     (size_t)(L + 1 + ccm::kTrThreads) * sizeof(int), stream, nbr_idx, nbr_w, lib_E,
+                     L, k_max, tau, csr_off, csr_ent, csr_pos, csr_w, idx_m);
   hipLaunchKernelGGL(ccm::bw_pair_kernel, dim3(n_pairs), dim3(ccm::kBwThreads), 0, stream, ts, ld, L,
                      nbr_idx, nbr_w, lib_E, n_lib, k_max, tau, pair_lib, pair_tgt, grad_rho, yhat, H,
                      Gy, pair_ok);
   const int64_t rows = (int64_t)n_pairs * L;
   hipLaunchKernelGGL(ccm::bw_coef_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, stream,
                      ts, ld, L, lib_ts, nbr_idx, lib_E, k_max, tau, pair_lib, pair_tgt, n_pairs, H,
-                     pair_ok, coef);
+                     pair_ok, csr_pos, com, coT);
   hipLaunchKernelGGL(ccm::bw_scatter_kernel, dim3((L + 255) / 256, n_pairs), dim3(256), 0, stream, ts,
-                     ld, L, lib_ts, nbr_idx, nbr_w, lib_E, k_max, tau, pair_lib, n_pairs, H, Gy,
-                     pair_ok, coef, csr_off, csr_ent, tc, lc);
-  hipLaunchKernelGGL(ccm::bw_reduce_kernel, dim3((L + 255) / 256), dim3(256), 0, stream, ld, L,
-                     pair_lib, pair_tgt, n_pairs, pair_ok, tc, lc, grad_ts, grad_lib);
+                     ld, L, lib_ts, lib_E, k_max, tau, pair_lib, n_pairs, H, Gy, pair_ok, com, coT,
+                     csr_off, csr_ent, csr_w, idx_m, tc, lc);
+  hipLaunchKernelGGL(ccm::bw_reduce_kernel, dim3((L + ccm::kWave - 1) / ccm::kWave, ccm::kRedHash),
+                     dim3(ccm::kWave), 0, stream, ld, L, pair_lib, pair_tgt, n_pairs, pair_ok, tc, lc,
+                     grad_ts, grad_lib);
   return hipGetLastError();
 }

@@ -183,9 +183,9 @@ ccm_status ccm_embed(const float* ts, int64_t ld, int32_t L, const int32_t* ids,
   ccm_status st = CCM_OK;
   if (!check_series(fn, &st, ts, ld, L, tau)) return st;
   if (n < 0) return fail(CCM_EINVAL, fn, "n < 0");
-  if (n > 0 && (!ids || !emb)) return fail(CCM_EINVAL, fn, "ids or emb is NULL");
   if (E < 1 || E > CCM_E_MAX) return fail(CCM_ERANGE, fn, "E outside [1, CCM_E_MAX]");
   if ((int64_t)(E - 1) * tau >= L) return fail(CCM_ERANGE, fn, "(E-1)*tau >= L");
+  if (n > 0 && (!ids || !emb)) return fail(CCM_EINVAL, fn, "ids or emb is NULL");
   return device_status(fn, ccm_launch_embed(ts, ld, L, ids, n, E, tau, emb, (hipStream_t)stream));
 }
 

@@ -78,6 +78,10 @@ def test_argument_errors_return_status_before_device_work():
     # tau < 1, L too large
     assert lib.ccm_embed(fake, 8, 100, fake, 1, 2, 0, fake, _null()) == ccm.CCM_ERANGE
     assert lib.ccm_embed(fake, 8, 20000, fake, 1, 2, 1, fake, _null()) == ccm.CCM_ERANGE
+    # no embedded point ((E-1) tau >= L) is a range error even when the (empty) output is
+    # NULL; a NULL output with points to write is EINVAL
+    assert lib.ccm_embed(fake, 8, 10, fake, 2, 6, 2, _null(), _null()) == ccm.CCM_ERANGE
+    assert lib.ccm_embed(fake, 8, 11, fake, 2, 6, 2, _null(), _null()) == ccm.CCM_EINVAL
     # crossmap: workspace missing, targets past the panel, unknown precision
     assert lib.ccm_crossmap_rho(fake, 64, 100, fake, fake, fake, 4, 21, 1, 0, 64, 0, fake, _null(),
                                 _null(), 0, _null()) == ccm.CCM_EWORKSPACE

@@ -1,5 +1,6 @@
 """GPU adjoint (ccm_crossmap_rho_backward through torch.autograd) against the FP64 oracle
-gradient, on the 2048-series coupled logistic network with 256 random pairs."""
+gradient, on the 2048-series coupled logistic network with 256 random pairs, plus the exact
+invariances of the gradients on subsampled and padded tables."""
 import sys
 
 import numpy as np
@@ -88,3 +89,61 @@ def test_adjoint_zero_and_nan_pairs(ccm):
     assert torch.all(Y.grad[:, 5] == 0)
     assert torch.isfinite(Y.grad).all() and torch.isfinite(X.grad).all()
     assert Y.grad[:, 2].abs().sum() > 0 and X.grad[1].abs().sum() > 0 and X.grad[0].abs().sum() == 0
+
+
+def _check_invariances(gy, gx, y, x):
+    assert np.all(np.isfinite(gy)) and np.all(np.isfinite(gx))
+    assert abs(gy.sum()) <= 1e-5 * np.abs(gy).sum()
+    assert abs((y * gy).sum()) <= 1e-5 * np.abs(y * gy).sum()
+    if np.abs(gx).sum() > 0:
+        assert abs(gx.sum()) <= 1e-5 * np.abs(gx).sum()
+        assert abs((x * gx).sum()) <= 1e-5 * np.abs(x * gx).sum()
+
+
+def test_adjoint_subsampled_and_padded_tables(ccm):
+    # Whatever the table, rho is invariant to y -> a y + b and, through d / d_1, to
+    # x -> a x + b, so each pair's gradients obey sum_s g(s) = 0 and sum_s v(s) g(s) = 0
+    # exactly (P11, P12).  Checked on tables of library subsamples (one library with too
+    # few marked points is unusable: NaN and no gradient) and on a table whose rows lose
+    # their farthest entry to padding (-1, weight 0, the rest renormalised), which both
+    # directions treat as absent.
+    import torch
+
+    w = synth.make("logistic64")
+    ts = w.panel
+    L = ts.shape[0]
+    libs = np.array([3, 17, 40], dtype=np.int32)
+    lib_E = np.array([3, 2, 4], dtype=np.int32)
+    rng = np.random.default_rng(46)
+    mask = np.zeros((len(libs), L), dtype=np.uint8)
+    for r, n_keep in enumerate([4, 60, 9]):     # library 0: 4 points < k + 1 = 5
+        mask[r, rng.choice(L, size=n_keep, replace=False)] = 1
+    Y = torch.as_tensor(ts).cuda()
+    X = torch.as_tensor(np.ascontiguousarray(ts[:, libs].T)).cuda()
+    _say("adjoint on subsampled tables")
+    idx, wt, _ = ccm.knn(Y, libs, lib_E, k_max=5, cand_mask=torch.as_tensor(mask).cuda())
+    assert bool((idx[0] < 0).all())
+    rho = ccm.crossmap_rho(Y, idx, wt, lib_E).cpu().numpy()
+    assert np.all(np.isnan(rho[0]))
+    for r in range(len(libs)):
+        for j in (5, 33):
+            gt, gl = ccm.crossmap_rho_backward(Y, X, idx, wt, lib_E, [r], [j], torch.ones(1))
+            gy = gt[:, j].double().cpu().numpy()
+            gx = gl[r].double().cpu().numpy()
+            if r == 0:
+                assert not gy.any() and not gx.any()
+                continue
+            _check_invariances(gy, gx, ts[:, j].astype(np.float64),
+                               ts[:, libs[r]].astype(np.float64))
+    _say("adjoint on a table with padding entries")
+    idx, wt, _ = ccm.knn(Y, libs, lib_E, k_max=5)
+    rows = torch.arange(10, L, 7, device="cuda")
+    for r in range(len(libs)):
+        idx[r, rows, int(lib_E[r])] = -1                # the k-th (farthest) entry
+        wt[r, rows, int(lib_E[r])] = 0.0
+        # weights of the remaining entries sum to 1 again, so y -> a y + b stays exact
+        wt[r, rows] = wt[r, rows] / wt[r, rows].sum(dim=1, keepdim=True)
+    for r in range(len(libs)):
+        gt, gl = ccm.crossmap_rho_backward(Y, X, idx, wt, lib_E, [r], [21], torch.ones(1))
+        _check_invariances(gt[:, 21].double().cpu().numpy(), gl[r].double().cpu().numpy(),
+                           ts[:, 21].astype(np.float64), ts[:, libs[r]].astype(np.float64))

@@ -1,6 +1,7 @@
-"""Edge cases of the HIP path against the oracle, through the C ABI: lag tau = 2 in the
-cross-map (both precisions), the largest series the FP32 tile holds (L = 2475), long series
-in the table and optE kernels (sampled query rows), and empty inputs."""
+"""Edge cases of the HIP path against the oracle, through the C ABI: the delay embedding
+(bit-exact, every E and several lags), lag tau = 2 in the cross-map (both precisions), the
+largest series the FP32 tile holds (L = 2475), long series in the table and optE kernels
+(sampled query rows), and empty inputs."""
 import sys
 
 import numpy as np
@@ -40,6 +41,26 @@ def _check_rho(rho_g, rho_o, label, tol):
     d = np.abs(rho_g.astype(np.float64) - rho_o)[~np.isnan(rho_o)]
     print(f"{label}: |drho| max {d.max():.3e}")
     assert d.max() < tol, f"{label}: max |drho| {d.max()}"
+
+
+def test_embed_bit_exact(ccm):
+    w = synth.make("ratenet1024")
+    ts = w.panel
+    ids = np.array([0, 5, 1023, 512, 77], dtype=np.int32)
+    for E, tau in [(1, 1), (2, 1), (7, 1), (20, 1), (3, 2), (5, 3), (20, 4)]:
+        _say(f"embed E={E} tau={tau}, 5 series of L={ts.shape[0]}")
+        emb = ccm.embed(_cuda(ts), ids, E, tau).cpu().numpy()
+        assert emb.shape == (len(ids), ts.shape[0] - (E - 1) * tau, E)
+        for r, c in enumerate(ids):
+            assert np.array_equal(emb[r], O.embed(ts[:, c], E, tau)), (E, tau, c)
+    # the shortest series that still has a point, and one that has none (an error)
+    short = np.ascontiguousarray(ts[:11])
+    emb = ccm.embed(_cuda(short), ids[:2], 6, 2).cpu().numpy()
+    assert emb.shape == (2, 1, 6)
+    assert np.array_equal(emb[1], O.embed(short[:, ids[1]], 6, 2))
+    with pytest.raises(ccm.CCMError) as ei:
+        ccm.embed(_cuda(short[:10]), ids[:2], 6, 2)
+    assert ei.value.status == ccm.CCM_ERANGE
 
 
 def test_crossmap_tau2_both_precisions(ccm):
