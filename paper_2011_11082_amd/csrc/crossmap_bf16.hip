@@ -25,7 +25,9 @@
 //     unconditionally: a branch around them would make the compiler move all 128
 //     accumulators between AGPRs and VGPRs at every stage.
 //   * The stage loop is unrolled by two so the two B register sets alternate roles (each
-//     is stored to LDS, then reloaded two stages ahead) without register copies.
+//     is stored to LDS, then reloaded two stages ahead) without register copies.  Within a
+//     stage the fragments of k-step kk + 1 are read from LDS while the products of kk run
+//     (scheduling barriers keep the compiler from serialising reads and products again).
 //   * Table entries are pre-sorted per (library, 128-row chunk) by (stage, row quarter) and
 //     packed into 32 bits (row, column within stage, BF16 weight), so each wave scatters and
 //     clears only its own entries; their bucket offsets are wave-uniform loads.
@@ -227,20 +229,25 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
         R[q] = (brow_ok && st + 2 < nst) ? *(const uint4*)(ysrc + (size_t)(st + 2) * kStage + q * 8)
                                          : uint4{0, 0, 0, 0};
       const uint16_t* Bb = Bs + (size_t)buf * kBTN * kRS;
+      // fragments of k-step kk + 1 are read while the products of kk run
+      const uint16_t* ap = Aw + (lane & 31) * kRS + 8 * (lane >> 5);
+      const uint16_t* bp = Bb + (lane & 31) * kRS + 8 * (lane >> 5);
+      bf16x8 fa[2], fb0[2], fb1[2];
+      fa[0] = *(const bf16x8*)ap;
+      fb0[0] = *(const bf16x8*)bp;
+      fb1[0] = *(const bf16x8*)(bp + 32 * kRS);
 #pragma unroll
       for (int kk = 0; kk < kStage / 16; ++kk) {
-        bf16x8 af[1], bfr[2];
-#pragma unroll
-        for (int a = 0; a < 1; ++a)
-          af[a] = *(const bf16x8*)(Aw + (32 * a + (lane & 31)) * kRS + 16 * kk + 8 * (lane >> 5));
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-          bfr[b] = *(const bf16x8*)(Bb + (32 * b + (lane & 31)) * kRS + 16 * kk + 8 * (lane >> 5));
-#pragma unroll
-        for (int a = 0; a < 1; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+        const int c = kk & 1, n = c ^ 1;
+        if (kk + 1 < kStage / 16) {
+          fa[n] = *(const bf16x8*)(ap + 16 * (kk + 1));
+          fb0[n] = *(const bf16x8*)(bp + 16 * (kk + 1));
+          fb1[n] = *(const bf16x8*)(bp + 32 * kRS + 16 * (kk + 1));
+        }
+        __builtin_amdgcn_sched_barrier(0);   // keep the reads of kk + 1 ahead of these products
+        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[c], fb0[c], acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[c], fb1[c], acc[0][1], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
       }
       // clear this wave's nonzeros again (after its own reads, in program order)
       for (int e = e0 + lane; e < e1; e += kWave) Aw[(eo[e] & 31) * kRS + ((eo[e] >> 7) & 63)] = 0;
