@@ -150,6 +150,9 @@ ccm_status ccm_simplex_optE(const float* ts, int64_t ld, int32_t L, const int32_
  *   yhat_ij(t) = sum_k w_i[t,k] * ts[n_ik(t) * ld + j];  rho[i][j - tgt0] = Pearson over
  *   t = (E_i-1) tau .. L-1 of (ts[t * ld + j], yhat_ij(t)); NaN where a variance vanishes.
  *   precision CCM_PRECISION_FP32: FP32 products and sums per prediction, FP64 moments.
+ *     Up to L = 2475 each 16-target tile sits in LDS; longer series (to CCM_L_MAX) read a
+ *     global copy of the tile through L2, which the workspace then holds (n_tgt x L x 4
+ *     bytes plus 5.4 KB per 16 targets).
  *   precision CCM_PRECISION_BF16: target values and weights rounded to BF16, contracted on
  *   MFMA with FP32 accumulation; observed values FP32; FP64 moments.
  *   rho [n_lib][n_tgt]               output (row = library, column = target).
@@ -177,9 +180,9 @@ ccm_status ccm_crossmap_rho(const float* ts, int64_t ld, int32_t L, const int32_
  *   FP32 products and sums per prediction, FP64 moments; NaN where a variance vanishes.
  *   rho [n_lib][n_tgt], moments [n_lib][n_tgt][3] (nullable) as in ccm_crossmap_rho.
  *   Targets are grouped by E on the device (no host synchronisation).
- * Errors: EINVAL (nulls, sizes), ERANGE (E_lo, n_E, k_max, L), ENOTSUP (L > 2475),
- * EWORKSPACE.  Workspace: ccm_workspace_size(CCM_OP_CROSSMAP_TARGET_E, L, n_E * n_lib,
- * n_tgt, k_max).
+ *   Series longer than 2475 steps use the global tile copy as in ccm_crossmap_rho.
+ * Errors: EINVAL (nulls, sizes), ERANGE (E_lo, n_E, k_max, L), EWORKSPACE.  Workspace:
+ * ccm_workspace_size(CCM_OP_CROSSMAP_TARGET_E, L, n_E * n_lib, n_tgt, k_max).
  */
 ccm_status ccm_crossmap_rho_target_E(const float* ts, int64_t ld, int32_t L,
                                      const int32_t* nbr_idx, const float* nbr_w, int32_t n_lib,

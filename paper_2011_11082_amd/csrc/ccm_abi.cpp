@@ -20,17 +20,18 @@ hipError_t ccm_launch_simplex(const float* ts, int64_t ld, int L, const int* ids
 hipError_t ccm_launch_embed(const float* ts, int64_t ld, int L, const int* ids, int n, int E,
                             int tau, float* emb, hipStream_t stream);
 size_t ccm_gather_lds_bytes(int L);
+int ccm_gather_tile_in_lds(int L);
 hipError_t ccm_launch_crossmap_fp32(const float* ts, int64_t ld, int L, int tau, int tgt0,
                                     int n_tgt, const int* nbr_idx, const float* nbr_w,
                                     const int* lib_E, int n_lib, int k_max, float* rho,
                                     double* moments, uint32_t* poff, float* pw, int* lib_k,
-                                    int* order, hipStream_t stream);
+                                    int* order, float* gtile, double* gsum, hipStream_t stream);
 int ccm_target_E_max_tiles(int n_tgt);
 hipError_t ccm_launch_crossmap_fp32_target_E(
     const float* ts, int64_t ld, int L, int tau, int tgt0, int n_tgt, const int* nbr_idx,
     const float* nbr_w, int n_lib, int E_lo, int n_E, int k_max, const int* tgt_E, float* rho,
     double* moments, uint32_t* poff, float* pw, int* lib_k, int* table_E, int* perm, int* tiles,
-    int* ntiles, hipStream_t stream);
+    int* ntiles, float* gtile, double* gsum, hipStream_t stream);
 size_t ccm_bf16_lds_bytes();
 hipError_t ccm_launch_crossmap_bf16(const float* ts, int64_t ld, int L, int tau, int tgt0, int n_tgt,
                                     const int* nbr_idx, const float* nbr_w, const int* lib_E,
@@ -62,12 +63,14 @@ ccm_status device_status(const char* fn, hipError_t e) {
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Workspace of the FP32 cross-map: blocked tables (byte offsets, weights), lib_k, order.
+// Workspace of the FP32 cross-map: blocked tables (byte offsets, weights), lib_k, order, and
+// for series too long for the LDS tile a global copy of every target tile ([n_tiles][L][16]
+// floats) with its FP64 column sums ([n_tiles][2][21][16]).
 struct CrossmapWs {
-  size_t off_poff, off_pw, off_libk, off_order, total;
+  size_t off_poff, off_pw, off_libk, off_order, off_gtile, off_gsum, total;
 };
 
-CrossmapWs crossmap_ws(int L, int n_lib, int k_max) {
+CrossmapWs crossmap_ws(int L, int n_lib, int k_max, int n_tiles) {
   CrossmapWs w;
   const size_t nblk = (size_t)(L + 15) / 16;
   const size_t KSM = (size_t)(k_max + 3) / 4;
@@ -77,7 +80,10 @@ CrossmapWs crossmap_ws(int L, int n_lib, int k_max) {
   w.off_pw = align_up(w.off_poff + ent * 4);
   w.off_libk = align_up(w.off_pw + ent * 4);
   w.off_order = align_up(w.off_libk + (size_t)n_lib * 4);
-  w.total = align_up(w.off_order + (size_t)n_lib * 4);
+  w.off_gtile = align_up(w.off_order + (size_t)n_lib * 4);
+  const bool global_tile = !ccm_gather_tile_in_lds(L);
+  w.off_gsum = align_up(w.off_gtile + (global_tile ? (size_t)n_tiles * L * 16 * 4 : 0));
+  w.total = align_up(w.off_gsum + (global_tile ? (size_t)n_tiles * 2 * (CCM_E_MAX + 1) * 16 * 8 : 0));
   return w;
 }
 
@@ -90,7 +96,7 @@ struct TargetEWs {
 
 TargetEWs target_E_ws(int L, int n_tab, int n_tgt, int k_max) {
   TargetEWs w;
-  w.tab = crossmap_ws(L, n_tab, k_max);
+  w.tab = crossmap_ws(L, n_tab, k_max, ccm_target_E_max_tiles(n_tgt));
   w.off_tabE = w.tab.total;
   w.off_perm = align_up(w.off_tabE + (size_t)n_tab * 4);
   w.off_tiles = align_up(w.off_perm + (size_t)n_tgt * 4);
@@ -161,7 +167,7 @@ ccm_status ccm_workspace_size(int32_t op, int32_t L, int32_t n_lib, int32_t n_tg
       *bytes = align_up((size_t)n_lib * CCM_E_MAX * sizeof(double));
       return CCM_OK;
     case CCM_OP_CROSSMAP_FP32:
-      *bytes = crossmap_ws(L, n_lib, k_max).total;
+      *bytes = crossmap_ws(L, n_lib, k_max, (n_tgt + 15) / 16).total;
       return CCM_OK;
     case CCM_OP_CROSSMAP_BF16:
       *bytes = bf16_ws(L, n_lib, n_tgt).total;
@@ -268,9 +274,7 @@ ccm_status ccm_crossmap_rho(const float* ts, int64_t ld, int32_t L, const int32_
   if (k_max < 2 || k_max > CCM_K_MAX) return fail(CCM_EINVAL, fn, "k_max outside [2, CCM_K_MAX]");
   if (L < 4) return fail(CCM_ERANGE, fn, "L < 4");
   if (precision == CCM_PRECISION_FP32) {
-    if (ccm_gather_lds_bytes(L) + 16 * sizeof(int) > 160 * 1024)
-      return fail(CCM_ENOTSUP, fn, "L too large for the 16-target LDS tile (max 2475)");
-    CrossmapWs w = crossmap_ws(L, n_lib, k_max);
+    CrossmapWs w = crossmap_ws(L, n_lib, k_max, (n_tgt + 15) / 16);
     if (n_lib == 0 || n_tgt == 0) return CCM_OK;
     if (!ws || ws_bytes < w.total) return fail(CCM_EWORKSPACE, fn, "workspace too small");
     char* base = (char*)ws;
@@ -278,7 +282,8 @@ ccm_status ccm_crossmap_rho(const float* ts, int64_t ld, int32_t L, const int32_
         fn, ccm_launch_crossmap_fp32(ts, ld, L, tau, tgt0, n_tgt, nbr_idx, nbr_w, lib_E, n_lib, k_max,
                                      rho, moments, (uint32_t*)(base + w.off_poff),
                                      (float*)(base + w.off_pw), (int*)(base + w.off_libk),
-                                     (int*)(base + w.off_order), (hipStream_t)stream));
+                                     (int*)(base + w.off_order), (float*)(base + w.off_gtile),
+                                     (double*)(base + w.off_gsum), (hipStream_t)stream));
   }
   if (precision == CCM_PRECISION_BF16) {
     Bf16Ws w = bf16_ws(L, n_lib, n_tgt);
@@ -314,8 +319,6 @@ ccm_status ccm_crossmap_rho_target_E(const float* ts, int64_t ld, int32_t L,
   if (n_lib > 0 && n_tgt > 0 && (!nbr_idx || !nbr_w || !tgt_E || !rho))
     return fail(CCM_EINVAL, fn, "NULL array argument");
   if (L < 4) return fail(CCM_ERANGE, fn, "L < 4");
-  if (ccm_gather_lds_bytes(L) + 16 * sizeof(int) > 160 * 1024)
-    return fail(CCM_ENOTSUP, fn, "L too large for the 16-target LDS tile (max 2475)");
   const TargetEWs w = target_E_ws(L, n_E * n_lib, n_tgt, k_max);
   if (n_lib == 0 || n_tgt == 0) return CCM_OK;
   if (!ws || ws_bytes < w.total) return fail(CCM_EWORKSPACE, fn, "workspace too small");
@@ -325,7 +328,9 @@ ccm_status ccm_crossmap_rho_target_E(const float* ts, int64_t ld, int32_t L,
               ts, ld, L, tau, tgt0, n_tgt, nbr_idx, nbr_w, n_lib, E_lo, n_E, k_max, tgt_E, rho,
               moments, (uint32_t*)(base + w.tab.off_poff), (float*)(base + w.tab.off_pw),
               (int*)(base + w.tab.off_libk), (int*)(base + w.off_tabE), (int*)(base + w.off_perm),
-              (int*)(base + w.off_tiles), (int*)(base + w.off_ntiles), (hipStream_t)stream));
+              (int*)(base + w.off_tiles), (int*)(base + w.off_ntiles),
+              (float*)(base + w.tab.off_gtile), (double*)(base + w.tab.off_gsum),
+              (hipStream_t)stream));
 }
 
 ccm_status ccm_crossmap_rho_backward(const float* ts, int64_t ld, int32_t L, const float* lib_ts,

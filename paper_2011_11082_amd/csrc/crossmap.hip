@@ -339,6 +339,71 @@ __device__ __forceinline__ void gather_library(const char* smem, const uint32_t*
   }
 }
 
+// Long series (L > 2475, where the tile no longer fits in LDS): the tile of 16 target
+// columns is a compact copy in global memory ([tile][L][16] floats, written by
+// tile_copy_kernel with its FP64 column sums), read through L2.  The grid is then 1-D and
+// XCD-aware: workgroup b runs on XCD b mod 8, and all `splits` workgroups of one tile share
+// that XCD (and its L2) and are dispatched together.
+constexpr int kXcd = 8;
+
+// Target column of tile column c (c < 16) of tile T, -1 if none: columns 16 T + c, or the
+// targets grouped by E (tile list entry T = bucket, first position in perm, column count).
+__device__ __forceinline__ int tile_column(int T, int c, int n_tgt, const int* tiles,
+                                           const int* perm) {
+  if (tiles) {
+    const int* te = tiles + 3 * T;
+    return c < te[2] ? perm[te[1] + c] : -1;
+  }
+  const int j = T * kTJ + c;
+  return j < n_tgt ? j : -1;
+}
+
+// gtile[T][t][c] = Y(t, column c of tile T) (0 where no column), and the FP64 sums of y and
+// y^2 over t >= (E-1) tau for E = 1..20: gsum[T][0][E][c], gsum[T][1][E][c].  One workgroup
+// of 1024 threads per tile; a sum over t >= (E-1) tau is the column total less its first
+// (E-1) tau terms.
+constexpr int kCopyThreads = 1024;
+
+__global__ __launch_bounds__(kCopyThreads) void tile_copy_kernel(
+    const float* __restrict__ ts, int64_t ld, int L, int tau, int tgt0, int n_tgt,
+    const int* __restrict__ tiles, const int* __restrict__ ntiles, const int* __restrict__ perm,
+    float* __restrict__ gtile, double* __restrict__ gsum) {
+  __shared__ double part[2][kCopyThreads];
+  __shared__ int colmap[kTJ];
+  const int T = blockIdx.x;
+  if (tiles && T >= *ntiles) return;
+  if (threadIdx.x < kTJ) colmap[threadIdx.x] = tile_column(T, threadIdx.x, n_tgt, tiles, perm);
+  __syncthreads();
+  const int c = threadIdx.x & (kTJ - 1);
+  const int j = colmap[c];
+  float* out = gtile + (size_t)T * L * kTJ;
+  double a = 0.0, a2 = 0.0;
+  for (int g = threadIdx.x; g < L * kTJ; g += blockDim.x) {
+    const float v = j >= 0 ? ts[(int64_t)(g >> 4) * ld + tgt0 + j] : 0.0f;
+    out[g] = v;
+    a += v;
+    a2 += (double)v * v;
+  }
+  part[0][threadIdx.x] = a;
+  part[1][threadIdx.x] = a2;
+  __syncthreads();
+  if (threadIdx.x < 2 * kTJ) {
+    const int q = threadIdx.x / kTJ;   // 0: y, 1: y^2
+    double tot = 0.0;
+    for (int r = c; r < kCopyThreads; r += kTJ) tot += part[q][r];
+    double* o = gsum + ((size_t)T * 2 + q) * (kEMax + 1) * kTJ;
+    double pre = 0.0;
+    int t = 0;
+    for (int E = 1; E <= kEMax; ++E) {
+      for (; t < (E - 1) * tau && t < L; ++t) {
+        const double v = j >= 0 ? (double)ts[(int64_t)t * ld + tgt0 + j] : 0.0;
+        pre += q ? v * v : v;
+      }
+      o[E * kTJ + c] = tot - pre;
+    }
+  }
+}
+
 // Two ways to form a workgroup's 16 target columns and its tables:
 //   * tiles == NULL: columns j0..j0+15 (j0 = 16 * blockIdx.x), every library with its own
 //     table (library row i = order[li], table i);
@@ -346,53 +411,76 @@ __device__ __forceinline__ void gather_library(const char* smem, const uint32_t*
 //     position in perm, column count); column c is target perm[first + c], and library row
 //     i uses table b * n_lib + i, the library's table at the bucket's E.  Bucket n_E holds
 //     targets whose E has no table: their rho is NaN.  Entries past *ntiles exit at once.
+template <bool GT>
 __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
     const float* __restrict__ ts, int64_t ld, int L, int tau, int tgt0, int n_tgt,
     const uint32_t* __restrict__ poff, const float* __restrict__ pw, const int* __restrict__ order,
     const int* __restrict__ lib_k, int n_lib, int nblk, int KSM, float* __restrict__ rho,
     double* __restrict__ moments, const int* __restrict__ tiles, const int* __restrict__ ntiles,
-    const int* __restrict__ perm, int n_E) {
+    const int* __restrict__ perm, int n_E, const float* __restrict__ gtile,
+    const double* __restrict__ gsum, int n_tiles, int gsplits) {
   extern __shared__ __align__(16) char smem[];
-  float* tile = (float*)smem;
-  double* sy = (double*)(smem + (size_t)L * kRowBytes);      // [kEMax + 1][16]
-  double* syy = sy + (kEMax + 1) * kTJ;
   __shared__ int colmap[kTJ];   // target column of each tile column, -1 if none
-
+  // tile T and library split of this workgroup
+  int T, split, splits;
+  if constexpr (GT) {
+    const int b = blockIdx.x;
+    const int q = b / kXcd;
+    T = (q / gsplits) * kXcd + b % kXcd;
+    split = q % gsplits;
+    splits = gsplits;
+    if (T >= n_tiles) return;   // whole workgroup: the grid's last round of tiles
+  } else {
+    T = blockIdx.x;
+    split = blockIdx.y;
+    splits = gridDim.y;
+  }
   int vbase = 0;
   bool no_table = false;
   if (tiles) {
-    if ((int)blockIdx.x >= *ntiles) return;   // whole workgroup: past the tile list
-    const int* te = tiles + 3 * blockIdx.x;
-    const int b = te[0], first = te[1], cnt = te[2];
-    if (threadIdx.x < kTJ) colmap[threadIdx.x] = (int)threadIdx.x < cnt ? perm[first + threadIdx.x] : -1;
+    if (T >= *ntiles) return;   // whole workgroup: past the tile list
+    const int b = tiles[3 * T];
     vbase = b * n_lib;
     no_table = b >= n_E;
-  } else if (threadIdx.x < kTJ) {
-    const int j = blockIdx.x * kTJ + threadIdx.x;
-    colmap[threadIdx.x] = j < n_tgt ? j : -1;
   }
+  if (threadIdx.x < kTJ) colmap[threadIdx.x] = tile_column(T, threadIdx.x, n_tgt, tiles, perm);
   __syncthreads();
-  // load the tile (rows 0..L-1, 16 columns; missing columns read as 0)
-  for (int g = threadIdx.x; g < L * kTJ; g += blockDim.x) {
-    const int t = g >> 4;
-    const int j = colmap[g & 15];
-    tile[g] = j >= 0 ? ts[(int64_t)t * ld + tgt0 + j] : 0.0f;
-  }
-  __syncthreads();
-  // FP64 sums of y and y^2 over t >= (E-1) tau, per E and column
-  for (int g = threadIdx.x; g < kEMax * kTJ; g += blockDim.x) {
-    const int E = g / kTJ + 1;
-    const int c = g % kTJ;
-    double a = 0.0, a2 = 0.0;
-    for (int t = (E - 1) * tau; t < L; ++t) {
-      double v = tile[t * kTJ + c];
-      a += v;
-      a2 += v * v;
+  // the tile, [L][16] floats (64 bytes per time step), and its FP64 column sums of y and
+  // y^2 over t >= (E-1) tau, [2][kEMax + 1][16]: in LDS, or the global copy
+  auto tile_ptr = [&]() -> const char* {
+    if constexpr (GT) return (const char*)(gtile + (size_t)T * L * kTJ);
+    else return smem;
+  };
+  auto sums_ptr = [&]() -> const double* {
+    if constexpr (GT) return gsum + (size_t)T * 2 * (kEMax + 1) * kTJ;
+    else return (const double*)(smem + (size_t)L * kRowBytes);
+  };
+  if constexpr (!GT) {
+    float* tile = (float*)smem;
+    double* lsy = (double*)(smem + (size_t)L * kRowBytes);
+    double* lsyy = lsy + (kEMax + 1) * kTJ;
+    // load the tile (rows 0..L-1, 16 columns; missing columns read as 0)
+    for (int g = threadIdx.x; g < L * kTJ; g += blockDim.x) {
+      const int t = g >> 4;
+      const int j = colmap[g & 15];
+      tile[g] = j >= 0 ? ts[(int64_t)t * ld + tgt0 + j] : 0.0f;
     }
-    sy[E * kTJ + c] = a;
-    syy[E * kTJ + c] = a2;
+    __syncthreads();
+    // FP64 sums of y and y^2 over t >= (E-1) tau, per E and column
+    for (int g = threadIdx.x; g < kEMax * kTJ; g += blockDim.x) {
+      const int E = g / kTJ + 1;
+      const int c = g % kTJ;
+      double a = 0.0, a2 = 0.0;
+      for (int t = (E - 1) * tau; t < L; ++t) {
+        double v = tile[t * kTJ + c];
+        a += v;
+        a2 += v * v;
+      }
+      lsy[E * kTJ + c] = a;
+      lsyy[E * kTJ + c] = a2;
+    }
+    __syncthreads();
   }
-  __syncthreads();
 
   const int lane = lane_id();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -400,10 +488,9 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
   const int G = lane >> 2;
   const int l = lane & 3;
   const uint32_t laneoff = (uint32_t)l * 16;
-  const int splits = gridDim.y;
   const size_t libstride = (size_t)nblk * KSM * kWave;
 
-  for (int li = blockIdx.y + splits * wave; li < n_lib; li += splits * nw) {
+  for (int li = split + splits * wave; li < n_lib; li += splits * nw) {
     const int i = __builtin_amdgcn_readfirstlane(order ? order[li] : li);
     const int v = vbase + i;   // table of this library row
     const int k = no_table ? 0 : __builtin_amdgcn_readfirstlane(lib_k[v]);
@@ -429,7 +516,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
     const int b0 = lo >> 4;
     switch (k) {
 #define CCM_K(KK) \
-  case KK: gather_library<KK>(smem, po, pq, b0, nblk, KSM, L, G, laneoff, m); break;
+  case KK: gather_library<KK>(tile_ptr(), po, pq, b0, nblk, KSM, L, G, laneoff, m); break;
       CCM_K(2) CCM_K(3) CCM_K(4) CCM_K(5) CCM_K(6) CCM_K(7) CCM_K(8) CCM_K(9) CCM_K(10)
       CCM_K(11) CCM_K(12) CCM_K(13) CCM_K(14) CCM_K(15) CCM_K(16) CCM_K(17) CCM_K(18)
       CCM_K(19) CCM_K(20) CCM_K(21)
@@ -447,6 +534,8 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
       }
     }
     if (G == 0) {
+      const double* sy = sums_ptr();
+      const double* syy = sy + (kEMax + 1) * kTJ;
       const double n = (double)(L - lo);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
@@ -477,9 +566,9 @@ hipError_t gather_allow_lds() {
   static bool done = false;
   if (done) return hipSuccess;
   hipFuncAttributes fa;
-  hipError_t e = hipFuncGetAttributes(&fa, (const void*)gather_fp32_kernel);
+  hipError_t e = hipFuncGetAttributes(&fa, (const void*)gather_fp32_kernel<false>);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)gather_fp32_kernel,
+  e = hipFuncSetAttribute((const void*)gather_fp32_kernel<false>,
                           hipFuncAttributeMaxDynamicSharedMemorySize,
                           160 * 1024 - (int)fa.sharedSizeBytes);
   if (e == hipSuccess) done = true;
@@ -494,6 +583,55 @@ int gather_splits(int n_tiles, int n_lib) {
   if (splits > max_splits) splits = max_splits;
   return splits < 1 ? 1 : splits;
 }
+
+// Long series: 32 workgroups per tile (one per CU of an XCD), at most one library per wave.
+int gather_splits_global(int n_lib) {
+  const int per_wave = (n_lib + kGatherThreads / kWave - 1) / (kGatherThreads / kWave);
+  return per_wave < 1 ? 1 : (per_wave > 32 ? 32 : per_wave);
+}
+
+// Launch the gather on n_tiles tiles (library-E columns when tiles == NULL, else the tile
+// list), from LDS when the tile fits there, else from a global copy made first.
+hipError_t launch_gather(const float* ts, int64_t ld, int L, int tau, int tgt0, int n_tgt,
+                         const uint32_t* poff, const float* pw, const int* order, const int* lib_k,
+                         int n_lib, int nblk, int KSM, float* rho, double* moments,
+                         const int* tiles, const int* ntiles, const int* perm, int n_E,
+                         int n_tiles, float* gtile, double* gsum, hipStream_t stream);
+}  // namespace ccm
+
+extern "C" size_t ccm_gather_lds_bytes(int L);
+
+// 1 when the 16-target tile of L time steps (plus the column sums) fits in LDS.
+extern "C" int ccm_gather_tile_in_lds(int L) {
+  return ccm_gather_lds_bytes(L) + ccm::kTJ * sizeof(int) <= 160 * 1024 ? 1 : 0;
+}
+
+namespace ccm {
+hipError_t launch_gather(const float* ts, int64_t ld, int L, int tau, int tgt0, int n_tgt,
+                         const uint32_t* poff, const float* pw, const int* order, const int* lib_k,
+                         int n_lib, int nblk, int KSM, float* rho, double* moments,
+                         const int* tiles, const int* ntiles, const int* perm, int n_E,
+                         int n_tiles, float* gtile, double* gsum, hipStream_t stream) {
+  if (ccm_gather_tile_in_lds(L)) {
+    hipError_t e = gather_allow_lds();
+    if (e != hipSuccess) return e;
+    const int splits = gather_splits(n_tiles, n_lib);
+    hipLaunchKernelGGL(gather_fp32_kernel<false>, dim3(n_tiles, splits), dim3(kGatherThreads),
+                       ccm_gather_lds_bytes(L), stream, ts, ld, L, tau, tgt0, n_tgt, poff, pw,
+                       order, lib_k, n_lib, nblk, KSM, rho, moments, tiles, ntiles, perm, n_E,
+                       (const float*)nullptr, (const double*)nullptr, n_tiles, splits);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(tile_copy_kernel, dim3(n_tiles), dim3(kCopyThreads), 0, stream, ts, ld, L,
+                     tau, tgt0, n_tgt, tiles, ntiles, perm, gtile, gsum);
+  const int splits = gather_splits_global(n_lib);
+  const int64_t grid = (int64_t)((n_tiles + kXcd - 1) / kXcd) * kXcd * splits;
+  hipLaunchKernelGGL(gather_fp32_kernel<true>, dim3((unsigned)grid), dim3(kGatherThreads), 0,
+                     stream, ts, ld, L, tau, tgt0, n_tgt, poff, pw, order, lib_k, n_lib, nblk, KSM,
+                     rho, moments, tiles, ntiles, perm, n_E, (const float*)gtile,
+                     (const double*)gsum, n_tiles, splits);
+  return hipGetLastError();
+}
 }  // namespace ccm
 
 extern "C" hipError_t ccm_launch_order(const int* lib_k, int n_lib, int* order, hipStream_t stream) {
@@ -501,7 +639,7 @@ extern "C" hipError_t ccm_launch_order(const int* lib_k, int n_lib, int* order, 
   return hipGetLastError();
 }
 
-extern "C" size_t ccm_gather_lds_bytes(int L) {
+extern "C" size_t ccm_gather_lds_bytes(int L) {  // tile + column sums
   return (size_t)L * ccm::kRowBytes + 2 * (ccm::kEMax + 1) * ccm::kTJ * sizeof(double);
 }
 
@@ -510,7 +648,7 @@ extern "C" hipError_t ccm_launch_crossmap_fp32(const float* ts, int64_t ld, int 
                                                const float* nbr_w, const int* lib_E, int n_lib,
                                                int k_max, float* rho, double* moments,
                                                uint32_t* poff, float* pw, int* lib_k, int* order,
-                                               hipStream_t stream) {
+                                               float* gtile, double* gsum, hipStream_t stream) {
   if (n_lib == 0 || n_tgt == 0) return hipSuccess;
   const int nblk = (L + 15) / 16;
   const int KSM = (k_max + 3) / 4;
@@ -518,15 +656,10 @@ extern "C" hipError_t ccm_launch_crossmap_fp32(const float* ts, int64_t ld, int 
   hipLaunchKernelGGL(ccm::prep_tables_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0,
                      stream, nbr_idx, nbr_w, lib_E, n_lib, L, k_max, tau, nblk, KSM, poff, pw, lib_k);
   hipLaunchKernelGGL(ccm::order_kernel, dim3(1), dim3(256), 0, stream, lib_k, n_lib, order);
-  const size_t lds = ccm_gather_lds_bytes(L);
-  hipError_t e = ccm::gather_allow_lds();
-  if (e != hipSuccess) return e;
   const int n_tiles = (n_tgt + ccm::kTJ - 1) / ccm::kTJ;
-  const int splits = ccm::gather_splits(n_tiles, n_lib);
-  hipLaunchKernelGGL(ccm::gather_fp32_kernel, dim3(n_tiles, splits), dim3(ccm::kGatherThreads), lds,
-                     stream, ts, ld, L, tau, tgt0, n_tgt, poff, pw, order, lib_k, n_lib, nblk, KSM,
-                     rho, moments, nullptr, nullptr, nullptr, 0);
-  return hipGetLastError();
+  return ccm::launch_gather(ts, ld, L, tau, tgt0, n_tgt, poff, pw, order, lib_k, n_lib, nblk, KSM,
+                            rho, moments, nullptr, nullptr, nullptr, 0, n_tiles, gtile, gsum,
+                            stream);
 }
 
 // Maximum number of tile entries for n_tgt targets: every bucket may end in a partial tile.
@@ -538,7 +671,7 @@ extern "C" hipError_t ccm_launch_crossmap_fp32_target_E(
     const float* ts, int64_t ld, int L, int tau, int tgt0, int n_tgt, const int* nbr_idx,
     const float* nbr_w, int n_lib, int E_lo, int n_E, int k_max, const int* tgt_E, float* rho,
     double* moments, uint32_t* poff, float* pw, int* lib_k, int* table_E, int* perm, int* tiles,
-    int* ntiles, hipStream_t stream) {
+    int* ntiles, float* gtile, double* gsum, hipStream_t stream) {
   if (n_lib == 0 || n_tgt == 0) return hipSuccess;
   const int nblk = (L + 15) / 16;
   const int KSM = (k_max + 3) / 4;
@@ -551,13 +684,7 @@ extern "C" hipError_t ccm_launch_crossmap_fp32_target_E(
                      lib_k);
   hipLaunchKernelGGL(ccm::bucket_targets_kernel, dim3(1), dim3(ccm::kBucketThreads), 0, stream,
                      tgt_E, n_tgt, E_lo, n_E, perm, tiles, ntiles);
-  hipError_t e = ccm::gather_allow_lds();
-  if (e != hipSuccess) return e;
-  const int max_tiles = ccm_target_E_max_tiles(n_tgt);
-  const int splits = ccm::gather_splits(max_tiles, n_lib);
-  hipLaunchKernelGGL(ccm::gather_fp32_kernel, dim3(max_tiles, splits), dim3(ccm::kGatherThreads),
-                     ccm_gather_lds_bytes(L), stream, ts, ld, L, tau, tgt0, n_tgt, poff, pw,
-                     (const int*)nullptr, lib_k, n_lib, nblk, KSM, rho, moments, tiles, ntiles,
-                     perm, n_E);
-  return hipGetLastError();
+  return ccm::launch_gather(ts, ld, L, tau, tgt0, n_tgt, poff, pw, nullptr, lib_k, n_lib, nblk,
+                            KSM, rho, moments, tiles, ntiles, perm, n_E,
+                            ccm_target_E_max_tiles(n_tgt), gtile, gsum, stream);
 }

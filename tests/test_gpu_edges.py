@@ -1,7 +1,8 @@
 """Edge cases of the HIP path against the oracle, through the C ABI: the delay embedding
 (bit-exact, every E and several lags), lag tau = 2 in the cross-map (both precisions), the
-largest series the FP32 tile holds (L = 2475), long series in the table and optE kernels
-(sampled query rows), and empty inputs."""
+largest series the FP32 LDS tile holds (L = 2475), series beyond it (L = 3000: the tile is
+read from a global copy, in both the library-E and the per-target-E forms), long series in
+the table and optE kernels (sampled query rows), and empty inputs."""
 import sys
 
 import numpy as np
@@ -93,6 +94,30 @@ def test_crossmap_at_the_largest_fp32_tile(ccm):
     rho_o, idx_o, _, _ = O.ccm_block(ts, lib_ids, lib_E, 1, 0, 40, k_max=10)
     assert np.array_equal(idx.cpu().numpy(), idx_o)
     _check_rho(rho, rho_o, "L=2475", 1e-5)
+
+
+def test_crossmap_beyond_the_lds_tile(ccm):
+    L = 3000                                  # past 2475: the tile is read through L2
+    rng = np.random.default_rng(47)
+    ts = np.cumsum(rng.standard_normal((L, 40)), axis=0).astype(np.float32)
+    ts = ((ts - ts.mean(0)) / ts.std(0)).astype(np.float32)
+    lib_ids, lib_E = [0, 7, 33], np.array([2, 7, 20], dtype=np.int32)
+    tgt0, n_tgt = 3, 37                       # three tiles, the last one ragged
+    _say("crossmap L=3000 (global tile), 3 libraries x 37 targets")
+    idx, wt, _ = ccm.knn(_cuda(ts), lib_ids, lib_E, k_max=21)
+    rho, mom = ccm.crossmap_rho(_cuda(ts), idx, wt, lib_E, tgt0=tgt0, n_tgt=n_tgt,
+                                want_moments=True)
+    rho_o, idx_o, _, _ = O.ccm_block(ts, lib_ids, lib_E, 1, tgt0, n_tgt, k_max=21)
+    assert np.array_equal(idx.cpu().numpy(), idx_o)
+    _check_rho(rho.cpu().numpy(), rho_o, "L=3000", 1e-5)
+    assert np.all(np.isfinite(mom.cpu().numpy()))
+    _say("crossmap per-target E, L=3000 (global tile), 2 libraries x 37 targets")
+    tgt_E = rng.integers(3, 5, size=n_tgt).astype(np.int32)
+    idx, wt, _ = ccm.knn_all_E(_cuda(ts), lib_ids[:2], 3, 2, k_max=21)
+    rho = ccm.crossmap_rho_target_E(_cuda(ts), idx, wt, 2, tgt_E, E_lo=3, tgt0=tgt0,
+                                    n_tgt=n_tgt).cpu().numpy()
+    rho_o = O.crossmap_rho_target_E(ts, lib_ids[:2], tgt_E, 1, tgt0, n_tgt, k_max=21)
+    _check_rho(rho, rho_o, "L=3000 per-target E", 1e-5)
 
 
 def test_long_series_tables_and_optE(ccm):
