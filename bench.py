@@ -136,6 +136,8 @@ def main():
                     help="skip the CCM convergence test (tables over library subsamples)")
     ap.add_argument("--no-target-E", action="store_true",
                     help="skip the per-target-E form (optE of every series + all-E tables)")
+    ap.add_argument("--no-long-series", action="store_true",
+                    help="skip the step at the paper's recording lengths (L = 3,780 and 8,528)")
     ap.add_argument("--profile-steps", action="store_true",
                     help="no timing extras (for runs under rocprofv3)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -370,6 +372,45 @@ def main():
                           "us_per_pair": round(ea.elapsed_time(eb) * 1e3 / P, 2)}
         log(f"adjoint: {P} pairs backward {ea.elapsed_time(eb):.1f} ms")
         del X, gts, glib
+
+    # The whole step at the recording lengths of the paper's Subject6 (3,780) and Subject11
+    # (8,528) data, beyond the 16-target LDS tile (the gather then reads a global tile copy
+    # through L2): 512 libraries x 8,192 filtered-Poisson targets, one timed step each.
+    if not args.no_long_series and not args.profile_steps:
+        long_res = []
+        for Llong in (3780, 8528):
+            wl2 = synth.make("poisson8192", T=Llong)
+            ts2 = torch.as_tensor(wl2.panel, device=dev)
+            ids2 = torch.arange(512, dtype=torch.int32, device=dev)
+            for rep in range(2):   # one warm-up, one timed
+                e0, e1, e2, e3 = ev(), ev(), ev(), ev()
+                e0.record()
+                oE2, _ = ccm.simplex_optE(ts2, ids2, 1, 20, 1, 1)
+                e1.record()
+                i2, w2, _ = ccm.knn(ts2, ids2, oE2, 1, 0, 21, want_d2=False)
+                e2.record()
+                r2 = ccm.crossmap_rho(ts2, i2, w2, oE2)
+                e3.record()
+                torch.cuda.synchronize()
+            eb0, eb1 = ev(), ev()
+            eb0.record()
+            rb = ccm.crossmap_rho(ts2, i2, w2, oE2, precision=ccm.PRECISION_BF16)
+            eb1.record()
+            torch.cuda.synchronize()
+            n2 = 512 * ts2.shape[1]
+            t_step = e0.elapsed_time(e3)
+            long_res.append({
+                "L": Llong, "n_lib": 512, "n_tgt": int(ts2.shape[1]),
+                "step_ms": round(t_step, 3), "rate": round(n2 / (t_step * 1e-3), 1),
+                "optE_ms": round(e0.elapsed_time(e1), 3), "knn_ms": round(e1.elapsed_time(e2), 3),
+                "crossmap_fp32_ms": round(e2.elapsed_time(e3), 3),
+                "crossmap_bf16_ms": round(eb0.elapsed_time(eb1), 3),
+                "max_abs_drho_bf16_vs_fp32": float((rb - r2).abs().nan_to_num(0.0).max())})
+            log(f"long series L={Llong}: step {t_step:.1f} ms (optE {e0.elapsed_time(e1):.1f}, "
+                f"tables {e1.elapsed_time(e2):.1f}, FP32 cross-map {e2.elapsed_time(e3):.1f}, "
+                f"BF16 {eb0.elapsed_time(eb1):.1f})")
+            del ts2, i2, w2, r2, rb
+        res["long_series"] = long_res
 
     if not args.no_cpu_baseline and not args.profile_steps:
         log("timing the CPU oracle on a bounded sample")
