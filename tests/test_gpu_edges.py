@@ -111,6 +111,9 @@ def test_crossmap_beyond_the_lds_tile(ccm):
     assert np.array_equal(idx.cpu().numpy(), idx_o)
     _check_rho(rho.cpu().numpy(), rho_o, "L=3000", 1e-5)
     assert np.all(np.isfinite(mom.cpu().numpy()))
+    r16 = ccm.crossmap_rho(_cuda(ts), idx, wt, lib_E, tgt0=tgt0, n_tgt=n_tgt,
+                           precision=ccm.PRECISION_BF16)
+    _check_rho(r16.cpu().numpy(), rho_o, "L=3000 BF16", 5e-3)
     _say("crossmap per-target E, L=3000 (global tile), 2 libraries x 37 targets")
     tgt_E = rng.integers(3, 5, size=n_tgt).astype(np.int32)
     idx, wt, _ = ccm.knn_all_E(_cuda(ts), lib_ids[:2], 3, 2, k_max=21)
