@@ -49,10 +49,15 @@ def mfma_flops(lib_E, L: int, n_tgt: int) -> float:
 
 
 def source_hash(*names) -> str:
+    """Hash of the code of the named kernel sources: comment-only lines and blank lines are
+    left out, so editing a comment keeps the committed counter summary valid."""
     h = hashlib.sha1()
     for n in names:
         with open(os.path.join(ROOT, "paper_2011_11082_amd", "csrc", n), "rb") as f:
-            h.update(f.read())
+            for line in f:
+                t = line.strip()
+                if t and not t.startswith(b"//"):
+                    h.update(t + b"\n")
     return h.hexdigest()[:12]
 
 

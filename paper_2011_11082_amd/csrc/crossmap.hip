@@ -25,6 +25,8 @@
 //     column sums.  rho is formed in FP64.
 //   * Waves of every workgroup visit libraries in the same order (heaviest first), so the
 //     32 workgroups of one XCD read the same tables at about the same time and share L2.
+//   * Series longer than the LDS tile holds (L > 2475) read a global copy of the tile
+//     through L2 instead, with the same tables and arithmetic (see gather_fp32_kernel<true>).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
