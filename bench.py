@@ -310,12 +310,22 @@ def main():
                   "tables_all_E_ms": round(eb.elapsed_time(ec), 3),
                   "crossmap_ms": round(ec.elapsed_time(ed), 3)}
             del tidx, tw, rho_t
+        # the paper's own phase-1 protocol (first half = library, second half = prediction)
+        ea = ev(); ea.record()
+        optE_half, _ = ccm.simplex_optE(ts, all_ids, 1, wl.E_max, 1, 1, ccm.MODE_HALF)
+        eb = ev(); eb.record()
+        torch.cuda.synchronize()
+        tE["optE_all_series_half_split_ms"] = round(ea.elapsed_time(eb), 2)
+        tE["optE_half_split_agrees_with_loo"] = round(
+            float((optE_half == optE_all).float().mean()), 4)
+        del optE_half
         tE["n_series"] = N
         tE["n_tables"] = n_lib * wl.E_max
         tE["crossmap_rate"] = round(cross / (tE["crossmap_ms"] * 1e-3), 1)
         tE["optE_hist_all_series"] = torch.bincount(optE_all.long(), minlength=21)[1:].tolist()
         res["per_target_E"] = tE
-        log(f"per-target-E: optE of {N} series {tE['optE_all_series_ms']:.0f} ms, "
+        log(f"per-target-E: optE of {N} series {tE['optE_all_series_ms']:.0f} ms "
+            f"(half split {tE['optE_all_series_half_split_ms']:.0f} ms), "
             f"{tE['n_tables']} tables {tE['tables_all_E_ms']:.1f} ms, "
             f"cross-map {tE['crossmap_ms']:.1f} ms")
         del optE_all

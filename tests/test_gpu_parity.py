@@ -143,6 +143,18 @@ def test_optE_ratenet_sample_and_half_mode(ccm):
     _check_optE(optE.cpu().numpy(), rho.cpu().numpy(), oE, oR, "ratenet HALF")
 
 
+def test_optE_half_split_full_E_range_brain_sample(ccm):
+    # the paper's phase-1 protocol over E = 1..20 at tau = 1 on filtered-Poisson rates
+    w = synth.make("brain101729")
+    ids = np.array([0, 1, 77, 511, 4096, 50000, 101728], dtype=np.int32)
+    ts = np.ascontiguousarray(w.panel[:, ids])
+    _say("simplex HALF E=1..20, 7 brain101729 series")
+    optE, rho = ccm.simplex_optE(_cuda(ts), np.arange(len(ids), dtype=np.int32), 1, 20, 1, 1,
+                                 ccm.MODE_HALF)
+    oE, oR, _ = O.simplex_optE(ts, list(range(len(ids))), 1, 20, 1, 1, O.MODE_HALF)
+    _check_optE(optE.cpu().numpy(), rho.cpu().numpy(), oE, oR, "brain HALF")
+
+
 def test_optE_degenerate_constant(ccm):
     ts = np.ones((60, 2), dtype=np.float32)
     ts[:, 1] = np.arange(60) % 2
