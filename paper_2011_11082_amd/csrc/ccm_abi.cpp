@@ -21,6 +21,7 @@ hipError_t ccm_launch_embed(const float* ts, int64_t ld, int L, const int* ids, 
                             int tau, float* emb, hipStream_t stream);
 size_t ccm_gather_lds_bytes(int L);
 int ccm_gather_tile_in_lds(int L);
+int ccm_gather_tile_targets(int L);
 hipError_t ccm_launch_crossmap_fp32(const float* ts, int64_t ld, int L, int tau, int tgt0,
                                     int n_tgt, const int* nbr_idx, const float* nbr_w,
                                     const int* lib_E, int n_lib, int k_max, float* rho,
@@ -64,27 +65,35 @@ ccm_status device_status(const char* fn, hipError_t e) {
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Workspace of the FP32 cross-map: blocked tables (byte offsets, weights), lib_k, order, and
-// for series too long for the LDS tile a global copy of every target tile ([n_tiles][L][16]
-// floats) with its FP64 column sums ([n_tiles][2][21][16]).
+// for series too long for the LDS tile a global copy of every target tile ([n_tiles][L][tj]
+// floats, tj targets per tile) with its FP64 column sums ([n_tiles][2][21][tj]).
 struct CrossmapWs {
   size_t off_poff, off_pw, off_libk, off_order, off_gtile, off_gsum, total;
 };
 
-CrossmapWs crossmap_ws(int L, int n_lib, int k_max, int n_tiles) {
+CrossmapWs crossmap_ws(int L, int n_lib, int k_max, int n_tiles, int tj) {
   CrossmapWs w;
-  const size_t nblk = (size_t)(L + 15) / 16;
   const size_t KSM = (size_t)(k_max + 3) / 4;
-  // spare blocks after the last library: the gather prefetches block b + 1 unguarded
-  const size_t ent = ((size_t)n_lib * nblk + 3) * KSM * 64;
+  // tables blocked by 16 query rows (16-target tile) or 8 (32-target tile), with spare
+  // blocks after the last library: the gather prefetches block b + 1 unguarded
+  const size_t ent16 = ((size_t)n_lib * ((L + 15) / 16) + 3) * KSM * 64;
+  const size_t ent32 = ((size_t)n_lib * ((L + 7) / 8) + 3) * KSM * 32;
+  const size_t ent = ent16 > ent32 ? ent16 : ent32;
   w.off_poff = 0;
   w.off_pw = align_up(w.off_poff + ent * 4);
   w.off_libk = align_up(w.off_pw + ent * 4);
   w.off_order = align_up(w.off_libk + (size_t)n_lib * 4);
   w.off_gtile = align_up(w.off_order + (size_t)n_lib * 4);
   const bool global_tile = !ccm_gather_tile_in_lds(L);
-  w.off_gsum = align_up(w.off_gtile + (global_tile ? (size_t)n_tiles * L * 16 * 4 : 0));
-  w.total = align_up(w.off_gsum + (global_tile ? (size_t)n_tiles * 2 * (CCM_E_MAX + 1) * 16 * 8 : 0));
+  w.off_gsum = align_up(w.off_gtile + (global_tile ? (size_t)n_tiles * L * tj * 4 : 0));
+  w.total = align_up(w.off_gsum + (global_tile ? (size_t)n_tiles * 2 * (CCM_E_MAX + 1) * tj * 8 : 0));
   return w;
+}
+
+// The library-E cross-map: 16-target tiles in LDS, or 32-target tiles from the global copy.
+CrossmapWs fp32_ws(int L, int n_lib, int k_max, int n_tgt) {
+  const int tj = ccm_gather_tile_targets(L);
+  return crossmap_ws(L, n_lib, k_max, (n_tgt + tj - 1) / tj, tj);
 }
 
 // Workspace of the per-target-E cross-map: the FP32 workspace over n_tab = n_E * n_lib
@@ -96,7 +105,7 @@ struct TargetEWs {
 
 TargetEWs target_E_ws(int L, int n_tab, int n_tgt, int k_max) {
   TargetEWs w;
-  w.tab = crossmap_ws(L, n_tab, k_max, ccm_target_E_max_tiles(n_tgt));
+  w.tab = crossmap_ws(L, n_tab, k_max, ccm_target_E_max_tiles(n_tgt), 16);
   w.off_tabE = w.tab.total;
   w.off_perm = align_up(w.off_tabE + (size_t)n_tab * 4);
   w.off_tiles = align_up(w.off_perm + (size_t)n_tgt * 4);
@@ -167,7 +176,7 @@ ccm_status ccm_workspace_size(int32_t op, int32_t L, int32_t n_lib, int32_t n_tg
       *bytes = align_up((size_t)n_lib * CCM_E_MAX * sizeof(double));
       return CCM_OK;
     case CCM_OP_CROSSMAP_FP32:
-      *bytes = crossmap_ws(L, n_lib, k_max, (n_tgt + 15) / 16).total;
+      *bytes = fp32_ws(L, n_lib, k_max, n_tgt).total;
       return CCM_OK;
     case CCM_OP_CROSSMAP_BF16:
       *bytes = bf16_ws(L, n_lib, n_tgt).total;
@@ -274,7 +283,7 @@ ccm_status ccm_crossmap_rho(const float* ts, int64_t ld, int32_t L, const int32_
   if (k_max < 2 || k_max > CCM_K_MAX) return fail(CCM_EINVAL, fn, "k_max outside [2, CCM_K_MAX]");
   if (L < 4) return fail(CCM_ERANGE, fn, "L < 4");
   if (precision == CCM_PRECISION_FP32) {
-    CrossmapWs w = crossmap_ws(L, n_lib, k_max, (n_tgt + 15) / 16);
+    CrossmapWs w = fp32_ws(L, n_lib, k_max, n_tgt);
     if (n_lib == 0 || n_tgt == 0) return CCM_OK;
     if (!ws || ws_bytes < w.total) return fail(CCM_EWORKSPACE, fn, "workspace too small");
     char* base = (char*)ws;

@@ -31,13 +31,26 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "wave.h"
 
 namespace ccm {
 
-constexpr int kTJ = 16;                 // targets per tile
+constexpr int kTJ = 16;                 // targets per tile in LDS
 constexpr int kGatherThreads = 1024;    // 16 waves
 constexpr int kRowBytes = kTJ * 4;
+
+// Tile geometry for TJ targets per tile: LPR = TJ / 4 lanes per query row (each reads 16
+// bytes of a neighbour row), RB = 64 / LPR query rows per wave block, SLOT = 4 RB table
+// entries per slot of four steps, ROW bytes per time step of the tile.
+template <int TJ>
+struct Geo {
+  static constexpr int LPR = TJ / 4;
+  static constexpr int RB = kWave / LPR;
+  static constexpr int SLOT = RB * 4;
+  static constexpr int ROW = TJ * 4;
+};
 
 // ---------------------------------------------------------------------------------------
 // Library order: counting sort of libraries by k descending (k = 0: unusable, last).
@@ -67,15 +80,18 @@ __global__ __launch_bounds__(256) void order_kernel(const int* __restrict__ lib_
 
 // ---------------------------------------------------------------------------------------
 // Table preparation: per (library, t) row, reorder the k entries for bank quarters and
-// write them blocked as [lib][t/16][slot][G][l] (entry j = 4*slot + l of query t = 16b+G)
-// as LDS byte offsets + weights.  Padding entries point at row (t+j) mod 4 with weight 0.
+// write them blocked as [lib][t/RB][slot][G][l] (entry j = 4*slot + l of query t = RB b + G,
+// RB = 16 for the 16-target tile, 8 for the 32-target one) as tile byte offsets + weights.
+// Padding entries point at row (t+j) mod 4 with weight 0.
 // ---------------------------------------------------------------------------------------
+template <int TJ>
 __global__ __launch_bounds__(256) void prep_tables_kernel(
     const int* __restrict__ nbr_idx, const float* __restrict__ nbr_w, const int* __restrict__ lib_E,
     int n_lib, int L, int k_max, int tau, int nblk, int KSM, uint32_t* __restrict__ poff,
     float* __restrict__ pw, int* __restrict__ lib_k) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t per = (int64_t)nblk * 16;
+  using Gm = Geo<TJ>;
+  const int64_t per = (int64_t)nblk * Gm::RB;
   if (g >= (int64_t)n_lib * per) return;
   const int i = (int)(g / per);
   const int t = (int)(g % per);
@@ -119,16 +135,16 @@ __global__ __launch_bounds__(256) void prep_tables_kernel(
       sel[nsel++] = pick;
     }
   }
-  const int b = t / 16;
-  const int G = t % 16;
+  const int b = t / Gm::RB;
+  const int G = t % Gm::RB;
   for (int j = 0; j < KSM * 4; ++j) {
-    const size_t pos = (((size_t)i * nblk + b) * KSM + (j >> 2)) * kWave + G * 4 + (j & 3);
-    uint32_t o = (uint32_t)(((t + j) & 3) * kRowBytes);
+    const size_t pos = (((size_t)i * nblk + b) * KSM + (j >> 2)) * Gm::SLOT + G * 4 + (j & 3);
+    uint32_t o = (uint32_t)(((t + j) & 3) * Gm::ROW);
     float wv = 0.0f;
     if (j < nsel) {
       int m = sel[j];
       if (idx[m] >= 0) {
-        o = (uint32_t)idx[m] * kRowBytes;
+        o = (uint32_t)idx[m] * Gm::ROW;
         wv = w[m];
       }
     }
@@ -255,11 +271,13 @@ struct Slots {
   float4 wgt[KS];
 };
 
-template <int S, int KS>
+template <int S, int TJ, int KS>
 __device__ __forceinline__ void load_slot(const uint32_t* bo, const float* bw, int lane,
                                           Slots<KS>& e) {
-  e.off[S] = bo[S * kWave + lane];
-  e.wgt[S] = *(const float4*)(bw + S * kWave + (lane & ~3));
+  using Gm = Geo<TJ>;
+  const int q = (lane / Gm::LPR) * 4;   // first entry of this lane's query row
+  e.off[S] = bo[S * Gm::SLOT + q + (lane & 3)];
+  e.wgt[S] = *(const float4*)(bw + S * Gm::SLOT + q);
 }
 
 template <int J, int K>
@@ -275,7 +293,7 @@ __device__ __forceinline__ void pair_reads(const char* tile, const Slots<(K + 3)
 // One table row, software-pipelined by pairs of steps (reads of pair p+1 issued before the
 // products of pair p).  Once the products of a slot are done its registers are reloaded
 // with the same slot of the next block, a whole block ahead of use.
-template <int K, int J = 0>
+template <int K, int TJ, int J = 0>
 __device__ __forceinline__ void gather_row_pipe(const char* tile, Slots<(K + 3) / 4>& e,
                                                 const uint32_t* nbo, const float* nbw, int lane,
                                                 uint32_t laneoff, float4 (&ya)[2],
@@ -285,20 +303,20 @@ __device__ __forceinline__ void gather_row_pipe(const char* tile, Slots<(K + 3) 
     if constexpr (J + 2 < K) pair_reads<J + 2, K>(tile, e, laneoff, yb);
     fma4<J == 0>(acc, wcomp<(J & 3)>(e.wgt[S]), ya[0]);
     if constexpr (J + 1 < K) fma4<false>(acc, wcomp<((J + 1) & 3)>(e.wgt[S]), ya[1]);
-    if constexpr ((J + 2) % 4 == 0 || J + 2 >= K) load_slot<S>(nbo, nbw, lane, e);
-    gather_row_pipe<K, J + 2>(tile, e, nbo, nbw, lane, laneoff, yb, ya, acc);
+    if constexpr ((J + 2) % 4 == 0 || J + 2 >= K) load_slot<S, TJ>(nbo, nbw, lane, e);
+    gather_row_pipe<K, TJ, J + 2>(tile, e, nbo, nbw, lane, laneoff, yb, ya, acc);
   }
 }
 
-template <int K>
+template <int K, int TJ>
 __device__ __forceinline__ void gather_block(const char* smem, Slots<(K + 3) / 4>& e,
                                              const uint32_t* nbo, const float* nbw, int lane,
                                              uint32_t laneoff, int t, int L, Moments& m) {
   float4 acc, ya[2], yb[2];
   pair_reads<0, K>(smem, e, laneoff, ya);
-  gather_row_pipe<K>(smem, e, nbo, nbw, lane, laneoff, ya, yb, acc);
+  gather_row_pipe<K, TJ>(smem, e, nbo, nbw, lane, laneoff, ya, yb, acc);
   t = t < L ? t : L - 1;
-  const float4 yo = *(const float4*)(smem + laneoff + (uint32_t)t * kRowBytes);
+  const float4 yo = *(const float4*)(smem + laneoff + (uint32_t)t * Geo<TJ>::ROW);
   m.sp.x += acc.x; m.sp.y += acc.y; m.sp.z += acc.z; m.sp.w += acc.w;
   m.spp.x = fmaf(acc.x, acc.x, m.spp.x); m.spp.y = fmaf(acc.y, acc.y, m.spp.y);
   m.spp.z = fmaf(acc.z, acc.z, m.spp.z); m.spp.w = fmaf(acc.w, acc.w, m.spp.w);
@@ -306,57 +324,60 @@ __device__ __forceinline__ void gather_block(const char* smem, Slots<(K + 3) / 4
   m.syp.z = fmaf(yo.z, acc.z, m.syp.z); m.syp.w = fmaf(yo.w, acc.w, m.syp.w);
 }
 
-template <int K, int S = 0>
+template <int K, int TJ, int S = 0>
 __device__ __forceinline__ void load_all(const uint32_t* bo, const float* bw, int lane,
                                          Slots<(K + 3) / 4>& e) {
   if constexpr (S < (K + 3) / 4) {
-    load_slot<S>(bo, bw, lane, e);
-    load_all<K, S + 1>(bo, bw, lane, e);
+    load_slot<S, TJ>(bo, bw, lane, e);
+    load_all<K, TJ, S + 1>(bo, bw, lane, e);
   }
 }
 
 // One library against the tile; FP32 moment sums (16 rows per lane) are folded into FP64
 // every 16 blocks.  The workspace holds spare blocks after the last library, so the load of
 // block b + 1 is always in bounds.
-template <int K>
+template <int K, int TJ>
 __device__ __forceinline__ void gather_library(const char* smem, const uint32_t* __restrict__ po,
                                                const float* __restrict__ pq, int b0, int nblk,
                                                int KSM, int L, int G, uint32_t laneoff,
                                                Moments& m) {
   const int lane = lane_id();
-  const size_t bstride = (size_t)KSM * kWave;
+  const size_t bstride = (size_t)KSM * Geo<TJ>::SLOT;
   const uint32_t* bo = po + (size_t)b0 * bstride;
   const float* bw = pq + (size_t)b0 * bstride;
   Slots<(K + 3) / 4> e;
-  load_all<K>(bo, bw, lane, e);
+  load_all<K, TJ>(bo, bw, lane, e);
   int b = b0;
   while (b < nblk) {
     const int bend = b + 16 < nblk ? b + 16 : nblk;
     for (; b < bend; ++b) {
       bo += bstride;
       bw += bstride;
-      gather_block<K>(smem, e, bo, bw, lane, laneoff, b * 16 + G, L, m);
+      gather_block<K, TJ>(smem, e, bo, bw, lane, laneoff, b * Geo<TJ>::RB + G, L, m);
     }
     fold(m);
   }
 }
 
-// Long series (L > 2475, where the tile no longer fits in LDS): the tile of 16 target
-// columns is a compact copy in global memory ([tile][L][16] floats, written by
-// tile_copy_kernel with its FP64 column sums), read through L2.  The grid is then 1-D and
-// XCD-aware: workgroup b runs on XCD b mod 8, and all `splits` workgroups of one tile share
-// that XCD (and its L2) and are dispatched together.
+// Long series (L > 2475, where the tile no longer fits in LDS): the tile of TJ target
+// columns is a compact copy in global memory ([tile][L][TJ] floats, written by
+// tile_copy_kernel with its FP64 column sums), read through L2.  With TJ = 32 a time step
+// of the tile is a whole 128-byte line and every table is read once per 32 targets.  The
+// grid is then 1-D and XCD-aware: workgroup b runs on XCD b mod 8, and all `splits`
+// workgroups of one tile share that XCD (and its L2) and are dispatched together.
 constexpr int kXcd = 8;
 
-// Target column of tile column c (c < 16) of tile T, -1 if none: columns 16 T + c, or the
-// targets grouped by E (tile list entry T = bucket, first position in perm, column count).
+// Target column of tile column c (c < TJ) of tile T, -1 if none: columns TJ T + c, or the
+// targets grouped by E (tile list entry T = bucket, first position in perm, column count;
+// these tiles have 16 columns).
+template <int TJ>
 __device__ __forceinline__ int tile_column(int T, int c, int n_tgt, const int* tiles,
                                            const int* perm) {
   if (tiles) {
     const int* te = tiles + 3 * T;
     return c < te[2] ? perm[te[1] + c] : -1;
   }
-  const int j = T * kTJ + c;
+  const int j = T * TJ + c;
   return j < n_tgt ? j : -1;
 }
 
@@ -366,22 +387,23 @@ __device__ __forceinline__ int tile_column(int T, int c, int n_tgt, const int* t
 // (E-1) tau terms.
 constexpr int kCopyThreads = 1024;
 
+template <int TJ>
 __global__ __launch_bounds__(kCopyThreads) void tile_copy_kernel(
     const float* __restrict__ ts, int64_t ld, int L, int tau, int tgt0, int n_tgt,
     const int* __restrict__ tiles, const int* __restrict__ ntiles, const int* __restrict__ perm,
     float* __restrict__ gtile, double* __restrict__ gsum) {
   __shared__ double part[2][kCopyThreads];
-  __shared__ int colmap[kTJ];
+  __shared__ int colmap[TJ];
   const int T = blockIdx.x;
   if (tiles && T >= *ntiles) return;
-  if (threadIdx.x < kTJ) colmap[threadIdx.x] = tile_column(T, threadIdx.x, n_tgt, tiles, perm);
+  if (threadIdx.x < TJ) colmap[threadIdx.x] = tile_column<TJ>(T, threadIdx.x, n_tgt, tiles, perm);
   __syncthreads();
-  const int c = threadIdx.x & (kTJ - 1);
+  const int c = threadIdx.x & (TJ - 1);
   const int j = colmap[c];
-  float* out = gtile + (size_t)T * L * kTJ;
+  float* out = gtile + (size_t)T * L * TJ;
   double a = 0.0, a2 = 0.0;
-  for (int g = threadIdx.x; g < L * kTJ; g += blockDim.x) {
-    const float v = j >= 0 ? ts[(int64_t)(g >> 4) * ld + tgt0 + j] : 0.0f;
+  for (int g = threadIdx.x; g < L * TJ; g += blockDim.x) {
+    const float v = j >= 0 ? ts[(int64_t)(g / TJ) * ld + tgt0 + j] : 0.0f;
     out[g] = v;
     a += v;
     a2 += (double)v * v;
@@ -389,11 +411,11 @@ __global__ __launch_bounds__(kCopyThreads) void tile_copy_kernel(
   part[0][threadIdx.x] = a;
   part[1][threadIdx.x] = a2;
   __syncthreads();
-  if (threadIdx.x < 2 * kTJ) {
-    const int q = threadIdx.x / kTJ;   // 0: y, 1: y^2
+  if (threadIdx.x < 2 * TJ) {
+    const int q = threadIdx.x / TJ;   // 0: y, 1: y^2
     double tot = 0.0;
-    for (int r = c; r < kCopyThreads; r += kTJ) tot += part[q][r];
-    double* o = gsum + ((size_t)T * 2 + q) * (kEMax + 1) * kTJ;
+    for (int r = c; r < kCopyThreads; r += TJ) tot += part[q][r];
+    double* o = gsum + ((size_t)T * 2 + q) * (kEMax + 1) * TJ;
     double pre = 0.0;
     int t = 0;
     for (int E = 1; E <= kEMax; ++E) {
@@ -401,7 +423,7 @@ __global__ __launch_bounds__(kCopyThreads) void tile_copy_kernel(
         const double v = j >= 0 ? (double)ts[(int64_t)t * ld + tgt0 + j] : 0.0;
         pre += q ? v * v : v;
       }
-      o[E * kTJ + c] = tot - pre;
+      o[E * TJ + c] = tot - pre;
     }
   }
 }
@@ -413,7 +435,7 @@ __global__ __launch_bounds__(kCopyThreads) void tile_copy_kernel(
 //     position in perm, column count); column c is target perm[first + c], and library row
 //     i uses table b * n_lib + i, the library's table at the bucket's E.  Bucket n_E holds
 //     targets whose E has no table: their rho is NaN.  Entries past *ntiles exit at once.
-template <bool GT>
+template <bool GT, int TJ>
 __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
     const float* __restrict__ ts, int64_t ld, int L, int tau, int tgt0, int n_tgt,
     const uint32_t* __restrict__ poff, const float* __restrict__ pw, const int* __restrict__ order,
@@ -421,8 +443,10 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
     double* __restrict__ moments, const int* __restrict__ tiles, const int* __restrict__ ntiles,
     const int* __restrict__ perm, int n_E, const float* __restrict__ gtile,
     const double* __restrict__ gsum, int n_tiles, int gsplits) {
+  static_assert(GT || TJ == kTJ, "the LDS tile has 16 columns");
+  using Gm = Geo<TJ>;
   extern __shared__ __align__(16) char smem[];
-  __shared__ int colmap[kTJ];   // target column of each tile column, -1 if none
+  __shared__ int colmap[TJ];    // target column of each tile column, -1 if none
   // tile T and library split of this workgroup
   int T, split, splits;
   if constexpr (GT) {
@@ -445,16 +469,16 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
     vbase = b * n_lib;
     no_table = b >= n_E;
   }
-  if (threadIdx.x < kTJ) colmap[threadIdx.x] = tile_column(T, threadIdx.x, n_tgt, tiles, perm);
+  if (threadIdx.x < TJ) colmap[threadIdx.x] = tile_column<TJ>(T, threadIdx.x, n_tgt, tiles, perm);
   __syncthreads();
-  // the tile, [L][16] floats (64 bytes per time step), and its FP64 column sums of y and
-  // y^2 over t >= (E-1) tau, [2][kEMax + 1][16]: in LDS, or the global copy
+  // the tile, [L][TJ] floats (4 TJ bytes per time step), and its FP64 column sums of y and
+  // y^2 over t >= (E-1) tau, [2][kEMax + 1][TJ]: in LDS, or the global copy
   auto tile_ptr = [&]() -> const char* {
-    if constexpr (GT) return (const char*)(gtile + (size_t)T * L * kTJ);
+    if constexpr (GT) return (const char*)(gtile + (size_t)T * L * TJ);
     else return smem;
   };
   auto sums_ptr = [&]() -> const double* {
-    if constexpr (GT) return gsum + (size_t)T * 2 * (kEMax + 1) * kTJ;
+    if constexpr (GT) return gsum + (size_t)T * 2 * (kEMax + 1) * TJ;
     else return (const double*)(smem + (size_t)L * kRowBytes);
   };
   if constexpr (!GT) {
@@ -487,17 +511,17 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
   const int lane = lane_id();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int nw = blockDim.x / kWave;
-  const int G = lane >> 2;
-  const int l = lane & 3;
+  const int G = lane / Gm::LPR;   // query row of the block
+  const int l = lane % Gm::LPR;   // this lane reads targets 4l .. 4l + 3
   const uint32_t laneoff = (uint32_t)l * 16;
-  const size_t libstride = (size_t)nblk * KSM * kWave;
+  const size_t libstride = (size_t)nblk * KSM * Gm::SLOT;
 
   for (int li = split + splits * wave; li < n_lib; li += splits * nw) {
     const int i = __builtin_amdgcn_readfirstlane(order ? order[li] : li);
     const int v = vbase + i;   // table of this library row
     const int k = no_table ? 0 : __builtin_amdgcn_readfirstlane(lib_k[v]);
     if (k == 0) {
-      const int j = lane < kTJ ? colmap[lane] : -1;
+      const int j = lane < TJ ? colmap[lane] : -1;
       if (j >= 0) {
         rho[(size_t)i * n_tgt + j] = __builtin_nanf("");
         if (moments) {
@@ -515,19 +539,19 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
     m.sp = m.spp = m.syp = float4{0, 0, 0, 0};
 #pragma unroll
     for (int c = 0; c < 4; ++c) m.dp[c] = m.dpp[c] = m.dyp[c] = 0.0;
-    const int b0 = lo >> 4;
+    const int b0 = lo / Gm::RB;
     switch (k) {
 #define CCM_K(KK) \
-  case KK: gather_library<KK>(tile_ptr(), po, pq, b0, nblk, KSM, L, G, laneoff, m); break;
+  case KK: gather_library<KK, TJ>(tile_ptr(), po, pq, b0, nblk, KSM, L, G, laneoff, m); break;
       CCM_K(2) CCM_K(3) CCM_K(4) CCM_K(5) CCM_K(6) CCM_K(7) CCM_K(8) CCM_K(9) CCM_K(10)
       CCM_K(11) CCM_K(12) CCM_K(13) CCM_K(14) CCM_K(15) CCM_K(16) CCM_K(17) CCM_K(18)
       CCM_K(19) CCM_K(20) CCM_K(21)
 #undef CCM_K
       default: break;
     }
-    // reduce over the 16 groups (lanes with equal l)
+    // reduce over the query rows (lanes with equal l)
 #pragma unroll
-    for (int o = 4; o < kWave; o <<= 1) {
+    for (int o = Gm::LPR; o < kWave; o <<= 1) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         m.dp[c] += __shfl_xor(m.dp[c], o);
@@ -537,14 +561,14 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
     }
     if (G == 0) {
       const double* sy = sums_ptr();
-      const double* syy = sy + (kEMax + 1) * kTJ;
+      const double* syy = sy + (kEMax + 1) * TJ;
       const double n = (double)(L - lo);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int col = 4 * l + c;
         const int j = colmap[col];
         if (j >= 0) {
-          const double r = pearson_from_moments(n, sy[E * kTJ + col], syy[E * kTJ + col],
+          const double r = pearson_from_moments(n, sy[E * TJ + col], syy[E * TJ + col],
                                                 m.dp[c], m.dpp[c], m.dyp[c]);
           rho[(size_t)i * n_tgt + j] = (float)r;
           if (moments) {
@@ -568,9 +592,9 @@ hipError_t gather_allow_lds() {
   static bool done = false;
   if (done) return hipSuccess;
   hipFuncAttributes fa;
-  hipError_t e = hipFuncGetAttributes(&fa, (const void*)gather_fp32_kernel<false>);
+  hipError_t e = hipFuncGetAttributes(&fa, (const void*)gather_fp32_kernel<false, kTJ>);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)gather_fp32_kernel<false>,
+  e = hipFuncSetAttribute((const void*)gather_fp32_kernel<false, kTJ>,
                           hipFuncAttributeMaxDynamicSharedMemorySize,
                           160 * 1024 - (int)fa.sharedSizeBytes);
   if (e == hipSuccess) done = true;
@@ -592,13 +616,6 @@ int gather_splits_global(int n_lib) {
   return per_wave < 1 ? 1 : (per_wave > 32 ? 32 : per_wave);
 }
 
-// Launch the gather on n_tiles tiles (library-E columns when tiles == NULL, else the tile
-// list), from LDS when the tile fits there, else from a global copy made first.
-hipError_t launch_gather(const float* ts, int64_t ld, int L, int tau, int tgt0, int n_tgt,
-                         const uint32_t* poff, const float* pw, const int* order, const int* lib_k,
-                         int n_lib, int nblk, int KSM, float* rho, double* moments,
-                         const int* tiles, const int* ntiles, const int* perm, int n_E,
-                         int n_tiles, float* gtile, double* gsum, hipStream_t stream);
 }  // namespace ccm
 
 extern "C" size_t ccm_gather_lds_bytes(int L);
@@ -608,27 +625,36 @@ extern "C" int ccm_gather_tile_in_lds(int L) {
   return ccm_gather_lds_bytes(L) + ccm::kTJ * sizeof(int) <= 160 * 1024 ? 1 : 0;
 }
 
+// Targets per tile of the library-E cross-map: 16 in LDS, 32 from the global copy.
+extern "C" int ccm_gather_tile_targets(int L) {
+  return ccm_gather_tile_in_lds(L) ? ccm::kTJ : 2 * ccm::kTJ;
+}
+
 namespace ccm {
+// Launch the gather on n_tiles tiles of TJ targets (library-E columns when tiles == NULL,
+// else the tile list, whose tiles have 16 columns), from LDS when the tile fits there
+// (TJ = 16), else from a global copy made first.  The tables were blocked for TJ.
+template <int TJ>
 hipError_t launch_gather(const float* ts, int64_t ld, int L, int tau, int tgt0, int n_tgt,
                          const uint32_t* poff, const float* pw, const int* order, const int* lib_k,
                          int n_lib, int nblk, int KSM, float* rho, double* moments,
                          const int* tiles, const int* ntiles, const int* perm, int n_E,
                          int n_tiles, float* gtile, double* gsum, hipStream_t stream) {
-  if (ccm_gather_tile_in_lds(L)) {
+  if (TJ == kTJ && ccm_gather_tile_in_lds(L)) {
     hipError_t e = gather_allow_lds();
     if (e != hipSuccess) return e;
     const int splits = gather_splits(n_tiles, n_lib);
-    hipLaunchKernelGGL(gather_fp32_kernel<false>, dim3(n_tiles, splits), dim3(kGatherThreads),
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gather_fp32_kernel<false, kTJ>), dim3(n_tiles, splits), dim3(kGatherThreads),
                        ccm_gather_lds_bytes(L), stream, ts, ld, L, tau, tgt0, n_tgt, poff, pw,
                        order, lib_k, n_lib, nblk, KSM, rho, moments, tiles, ntiles, perm, n_E,
                        (const float*)nullptr, (const double*)nullptr, n_tiles, splits);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(tile_copy_kernel, dim3(n_tiles), dim3(kCopyThreads), 0, stream, ts, ld, L,
+  hipLaunchKernelGGL(tile_copy_kernel<TJ>, dim3(n_tiles), dim3(kCopyThreads), 0, stream, ts, ld, L,
                      tau, tgt0, n_tgt, tiles, ntiles, perm, gtile, gsum);
   const int splits = gather_splits_global(n_lib);
   const int64_t grid = (int64_t)((n_tiles + kXcd - 1) / kXcd) * kXcd * splits;
-  hipLaunchKernelGGL(gather_fp32_kernel<true>, dim3((unsigned)grid), dim3(kGatherThreads), 0,
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(gather_fp32_kernel<true, TJ>), dim3((unsigned)grid), dim3(kGatherThreads), 0,
                      stream, ts, ld, L, tau, tgt0, n_tgt, poff, pw, order, lib_k, n_lib, nblk, KSM,
                      rho, moments, tiles, ntiles, perm, n_E, (const float*)gtile,
                      (const double*)gsum, n_tiles, splits);
@@ -652,16 +678,23 @@ extern "C" hipError_t ccm_launch_crossmap_fp32(const float* ts, int64_t ld, int 
                                                uint32_t* poff, float* pw, int* lib_k, int* order,
                                                float* gtile, double* gsum, hipStream_t stream) {
   if (n_lib == 0 || n_tgt == 0) return hipSuccess;
-  const int nblk = (L + 15) / 16;
   const int KSM = (k_max + 3) / 4;
-  const int64_t rows = (int64_t)n_lib * nblk * 16;
-  hipLaunchKernelGGL(ccm::prep_tables_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0,
-                     stream, nbr_idx, nbr_w, lib_E, n_lib, L, k_max, tau, nblk, KSM, poff, pw, lib_k);
-  hipLaunchKernelGGL(ccm::order_kernel, dim3(1), dim3(256), 0, stream, lib_k, n_lib, order);
-  const int n_tiles = (n_tgt + ccm::kTJ - 1) / ccm::kTJ;
-  return ccm::launch_gather(ts, ld, L, tau, tgt0, n_tgt, poff, pw, order, lib_k, n_lib, nblk, KSM,
-                            rho, moments, nullptr, nullptr, nullptr, 0, n_tiles, gtile, gsum,
-                            stream);
+  auto run = [&](auto tj) -> hipError_t {
+    constexpr int TJ = decltype(tj)::value;
+    constexpr int RB = ccm::Geo<TJ>::RB;
+    const int nblk = (L + RB - 1) / RB;
+    const int64_t rows = (int64_t)n_lib * nblk * RB;
+    hipLaunchKernelGGL(ccm::prep_tables_kernel<TJ>, dim3((unsigned)((rows + 255) / 256)), dim3(256),
+                       0, stream, nbr_idx, nbr_w, lib_E, n_lib, L, k_max, tau, nblk, KSM, poff, pw,
+                       lib_k);
+    hipLaunchKernelGGL(ccm::order_kernel, dim3(1), dim3(256), 0, stream, lib_k, n_lib, order);
+    const int n_tiles = (n_tgt + TJ - 1) / TJ;
+    return ccm::launch_gather<TJ>(ts, ld, L, tau, tgt0, n_tgt, poff, pw, order, lib_k, n_lib,
+                                  nblk, KSM, rho, moments, nullptr, nullptr, nullptr, 0, n_tiles,
+                                  gtile, gsum, stream);
+  };
+  if (ccm_gather_tile_targets(L) == ccm::kTJ) return run(std::integral_constant<int, ccm::kTJ>{});
+  return run(std::integral_constant<int, 2 * ccm::kTJ>{});
 }
 
 // Maximum number of tile entries for n_tgt targets: every bucket may end in a partial tile.
@@ -681,12 +714,12 @@ extern "C" hipError_t ccm_launch_crossmap_fp32_target_E(
   hipLaunchKernelGGL(ccm::fill_table_E_kernel, dim3((n_tab + 255) / 256), dim3(256), 0, stream,
                      table_E, n_lib, E_lo, n_tab);
   const int64_t rows = (int64_t)n_tab * nblk * 16;
-  hipLaunchKernelGGL(ccm::prep_tables_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0,
+  hipLaunchKernelGGL(ccm::prep_tables_kernel<ccm::kTJ>, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0,
                      stream, nbr_idx, nbr_w, table_E, n_tab, L, k_max, tau, nblk, KSM, poff, pw,
                      lib_k);
   hipLaunchKernelGGL(ccm::bucket_targets_kernel, dim3(1), dim3(ccm::kBucketThreads), 0, stream,
                      tgt_E, n_tgt, E_lo, n_E, perm, tiles, ntiles);
-  return ccm::launch_gather(ts, ld, L, tau, tgt0, n_tgt, poff, pw, nullptr, lib_k, n_lib, nblk,
+  return ccm::launch_gather<ccm::kTJ>(ts, ld, L, tau, tgt0, n_tgt, poff, pw, nullptr, lib_k, n_lib, nblk,
                             KSM, rho, moments, tiles, ntiles, perm, n_E,
                             ccm_target_E_max_tiles(n_tgt), gtile, gsum, stream);
 }
