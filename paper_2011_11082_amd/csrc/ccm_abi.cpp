@@ -27,7 +27,7 @@ hipError_t ccm_launch_crossmap_fp32(const float* ts, int64_t ld, int L, int tau,
                                     const int* lib_E, int n_lib, int k_max, float* rho,
                                     double* moments, uint32_t* poff, float* pw, int* lib_k,
                                     int* order, float* gtile, double* gsum, hipStream_t stream);
-int ccm_target_E_max_tiles(int n_tgt);
+int ccm_target_E_max_tiles(int n_tgt, int tj);
 hipError_t ccm_launch_crossmap_fp32_target_E(
     const float* ts, int64_t ld, int L, int tau, int tgt0, int n_tgt, const int* nbr_idx,
     const float* nbr_w, int n_lib, int E_lo, int n_E, int k_max, const int* tgt_E, float* rho,
@@ -105,11 +105,12 @@ struct TargetEWs {
 
 TargetEWs target_E_ws(int L, int n_tab, int n_tgt, int k_max) {
   TargetEWs w;
-  w.tab = crossmap_ws(L, n_tab, k_max, ccm_target_E_max_tiles(n_tgt), 16);
+  const int tj = ccm_gather_tile_targets(L);
+  w.tab = crossmap_ws(L, n_tab, k_max, ccm_target_E_max_tiles(n_tgt, tj), tj);
   w.off_tabE = w.tab.total;
   w.off_perm = align_up(w.off_tabE + (size_t)n_tab * 4);
   w.off_tiles = align_up(w.off_perm + (size_t)n_tgt * 4);
-  w.off_ntiles = align_up(w.off_tiles + (size_t)ccm_target_E_max_tiles(n_tgt) * 3 * 4);
+  w.off_ntiles = align_up(w.off_tiles + (size_t)ccm_target_E_max_tiles(n_tgt, tj) * 3 * 4);
   w.total = align_up(w.off_ntiles + 4);
   return w;
 }

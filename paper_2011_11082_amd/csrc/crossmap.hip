@@ -157,11 +157,12 @@ __global__ __launch_bounds__(256) void prep_tables_kernel(
 // Targets grouped by E (the paper's Alg. 2 as printed: each target is cross-mapped with the
 // libraries' tables at the target's own E).  One workgroup: a stable counting sort of the
 // targets into buckets b = E - E_lo (bucket n_E: E without a table), then the tile list
-// (bucket, first position, column count) with at most 16 columns per tile.
+// (bucket, first position, column count) with at most TJ columns per tile.
 // ---------------------------------------------------------------------------------------
 constexpr int kBucketThreads = 512;
 constexpr int kBuckets = kEMax + 1;
 
+template <int TJ>
 __global__ __launch_bounds__(kBucketThreads) void bucket_targets_kernel(
     const int* __restrict__ tgt_E, int n_tgt, int E_lo, int n_E, int* __restrict__ perm,
     int* __restrict__ tiles, int* __restrict__ ntiles) {
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(kBucketThreads) void bucket_targets_kernel(
       bstart[b] = pos;
       tstart[b] = tl;
       pos += c;
-      tl += (c + kTJ - 1) / kTJ;
+      tl += (c + TJ - 1) / TJ;
     }
     bstart[kBuckets] = pos;
     tstart[kBuckets] = tl;
@@ -213,8 +214,8 @@ __global__ __launch_bounds__(kBucketThreads) void bucket_targets_kernel(
     const int m = T - tstart[b];
     const int size = bstart[b + 1] - bstart[b];
     tiles[3 * T] = b;
-    tiles[3 * T + 1] = bstart[b] + m * kTJ;
-    tiles[3 * T + 2] = min(kTJ, size - m * kTJ);
+    tiles[3 * T + 1] = bstart[b] + m * TJ;
+    tiles[3 * T + 2] = min(TJ, size - m * TJ);
   }
 }
 
@@ -368,8 +369,7 @@ __device__ __forceinline__ void gather_library(const char* smem, const uint32_t*
 constexpr int kXcd = 8;
 
 // Target column of tile column c (c < TJ) of tile T, -1 if none: columns TJ T + c, or the
-// targets grouped by E (tile list entry T = bucket, first position in perm, column count;
-// these tiles have 16 columns).
+// targets grouped by E (tile list entry T = bucket, first position in perm, column count).
 template <int TJ>
 __device__ __forceinline__ int tile_column(int T, int c, int n_tgt, const int* tiles,
                                            const int* perm) {
@@ -625,15 +625,15 @@ extern "C" int ccm_gather_tile_in_lds(int L) {
   return ccm_gather_lds_bytes(L) + ccm::kTJ * sizeof(int) <= 160 * 1024 ? 1 : 0;
 }
 
-// Targets per tile of the library-E cross-map: 16 in LDS, 32 from the global copy.
+// Targets per tile of the cross-map: 16 in LDS, 32 from the global copy.
 extern "C" int ccm_gather_tile_targets(int L) {
   return ccm_gather_tile_in_lds(L) ? ccm::kTJ : 2 * ccm::kTJ;
 }
 
 namespace ccm {
 // Launch the gather on n_tiles tiles of TJ targets (library-E columns when tiles == NULL,
-// else the tile list, whose tiles have 16 columns), from LDS when the tile fits there
-// (TJ = 16), else from a global copy made first.  The tables were blocked for TJ.
+// else the tile list), from LDS when the tile fits there (TJ = 16), else from a global copy
+// made first.  The tables were blocked for TJ.
 template <int TJ>
 hipError_t launch_gather(const float* ts, int64_t ld, int L, int tau, int tgt0, int n_tgt,
                          const uint32_t* poff, const float* pw, const int* order, const int* lib_k,
@@ -697,9 +697,10 @@ extern "C" hipError_t ccm_launch_crossmap_fp32(const float* ts, int64_t ld, int 
   return run(std::integral_constant<int, 2 * ccm::kTJ>{});
 }
 
-// Maximum number of tile entries for n_tgt targets: every bucket may end in a partial tile.
-extern "C" int ccm_target_E_max_tiles(int n_tgt) {
-  return (n_tgt + ccm::kTJ - 1) / ccm::kTJ + ccm::kBuckets;
+// Maximum number of tile entries for n_tgt targets in tiles of tj columns: every bucket may
+// end in a partial tile.
+extern "C" int ccm_target_E_max_tiles(int n_tgt, int tj) {
+  return (n_tgt + tj - 1) / tj + ccm::kBuckets;
 }
 
 extern "C" hipError_t ccm_launch_crossmap_fp32_target_E(
@@ -708,18 +709,24 @@ extern "C" hipError_t ccm_launch_crossmap_fp32_target_E(
     double* moments, uint32_t* poff, float* pw, int* lib_k, int* table_E, int* perm, int* tiles,
     int* ntiles, float* gtile, double* gsum, hipStream_t stream) {
   if (n_lib == 0 || n_tgt == 0) return hipSuccess;
-  const int nblk = (L + 15) / 16;
   const int KSM = (k_max + 3) / 4;
   const int n_tab = n_E * n_lib;
   hipLaunchKernelGGL(ccm::fill_table_E_kernel, dim3((n_tab + 255) / 256), dim3(256), 0, stream,
                      table_E, n_lib, E_lo, n_tab);
-  const int64_t rows = (int64_t)n_tab * nblk * 16;
-  hipLaunchKernelGGL(ccm::prep_tables_kernel<ccm::kTJ>, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0,
-                     stream, nbr_idx, nbr_w, table_E, n_tab, L, k_max, tau, nblk, KSM, poff, pw,
-                     lib_k);
-  hipLaunchKernelGGL(ccm::bucket_targets_kernel, dim3(1), dim3(ccm::kBucketThreads), 0, stream,
-                     tgt_E, n_tgt, E_lo, n_E, perm, tiles, ntiles);
-  return ccm::launch_gather<ccm::kTJ>(ts, ld, L, tau, tgt0, n_tgt, poff, pw, nullptr, lib_k, n_lib, nblk,
-                            KSM, rho, moments, tiles, ntiles, perm, n_E,
-                            ccm_target_E_max_tiles(n_tgt), gtile, gsum, stream);
+  auto run = [&](auto tj) -> hipError_t {
+    constexpr int TJ = decltype(tj)::value;
+    constexpr int RB = ccm::Geo<TJ>::RB;
+    const int nblk = (L + RB - 1) / RB;
+    const int64_t rows = (int64_t)n_tab * nblk * RB;
+    hipLaunchKernelGGL(ccm::prep_tables_kernel<TJ>, dim3((unsigned)((rows + 255) / 256)), dim3(256),
+                       0, stream, nbr_idx, nbr_w, table_E, n_tab, L, k_max, tau, nblk, KSM, poff,
+                       pw, lib_k);
+    hipLaunchKernelGGL(ccm::bucket_targets_kernel<TJ>, dim3(1), dim3(ccm::kBucketThreads), 0,
+                       stream, tgt_E, n_tgt, E_lo, n_E, perm, tiles, ntiles);
+    return ccm::launch_gather<TJ>(ts, ld, L, tau, tgt0, n_tgt, poff, pw, nullptr, lib_k, n_lib,
+                                  nblk, KSM, rho, moments, tiles, ntiles, perm, n_E,
+                                  ccm_target_E_max_tiles(n_tgt, TJ), gtile, gsum, stream);
+  };
+  if (ccm_gather_tile_targets(L) == ccm::kTJ) return run(std::integral_constant<int, ccm::kTJ>{});
+  return run(std::integral_constant<int, 2 * ccm::kTJ>{});
 }
