@@ -407,17 +407,9 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
   int* csr_pos = (int*)((char*)csr_ent + tb);
   float* csr_w = (float*)((char*)csr_pos + tb);
   int* idx_m = (int*)((char*)csr_w + tb);
-  static bool attr = false;
-  if (!attr) {
-    hipFuncAttributes fa;
-    hipError_t e = hipFuncGetAttributes(&fa, (const void*)ccm::bw_transpose_kernel);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)ccm::bw_transpose_kernel,
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024 - (int)fa.sharedSizeBytes);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static std::atomic<uint64_t> attr{0};
+  hipError_t e = ccm::allow_lds_once((const void*)ccm::bw_transpose_kernel, attr);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(ccm::bw_transpose_kernel, dim3(n_lib), dim3(ccm::kTrThreads),
                      (size_t)(L + 1 + ccm::kTrThreads) * sizeof(int), stream, nbr_idx, nbr_w, lib_E,
                      L, k_max, tau, csr_off, csr_ent, csr_pos, csr_w, idx_m);

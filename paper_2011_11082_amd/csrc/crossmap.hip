@@ -589,16 +589,8 @@ namespace ccm {
 // The gather's LDS tile needs more than the default dynamic LDS limit: allow all of the
 // CU's 160 KB minus the kernel's static LDS.
 hipError_t gather_allow_lds() {
-  static bool done = false;
-  if (done) return hipSuccess;
-  hipFuncAttributes fa;
-  hipError_t e = hipFuncGetAttributes(&fa, (const void*)gather_fp32_kernel<false, kTJ>);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)gather_fp32_kernel<false, kTJ>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize,
-                          160 * 1024 - (int)fa.sharedSizeBytes);
-  if (e == hipSuccess) done = true;
-  return e;
+  static std::atomic<uint64_t> done{0};
+  return allow_lds_once((const void*)gather_fp32_kernel<false, kTJ>, done);
 }
 
 // Library splits (grid.y): enough workgroups to fill the chip when there are few tiles, no

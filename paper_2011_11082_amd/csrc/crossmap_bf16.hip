@@ -368,13 +368,9 @@ extern "C" hipError_t ccm_launch_crossmap_bf16(const float* ts, int64_t ld, int 
                      nbr_idx, nbr_w, lib_E, L, k_max, tau, nchunk_max, nst, ent, stage_off, lib_k);
   hipError_t e = ccm_launch_order(lib_k, n_lib, order, stream);
   if (e != hipSuccess) return e;
-  static bool attr = false;
-  if (!attr) {
-    e = hipFuncSetAttribute((const void*)ccm::gather_bf16_kernel,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)ccm_bf16_lds_bytes());
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static std::atomic<uint64_t> attr{0};
+  e = ccm::allow_lds_once((const void*)ccm::gather_bf16_kernel, attr, ccm_bf16_lds_bytes());
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(ccm::gather_bf16_kernel, dim3((n_lib + 1) / 2, (n_tgt + ccm::kBTN - 1) / ccm::kBTN),
                      dim3(ccm::kBThreads), ccm_bf16_lds_bytes(), stream, ts, ld, L, tau, tgt0, n_tgt,
                      Lpad, yt, ent, stage_off, order, lib_k, n_lib, nchunk_max, nst, rho, moments);

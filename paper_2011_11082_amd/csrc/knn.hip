@@ -542,16 +542,6 @@ __global__ void embed_kernel(const float* __restrict__ ts, int64_t ld, int L,
 // ---- launchers (called from the C ABI) ----------------------------------------------
 namespace ccm {
 // The series copy (and mask) of a long series exceeds the default 64 KB of dynamic LDS.
-hipError_t allow_lds(const void* kernel, bool& done) {
-  if (done) return hipSuccess;
-  hipFuncAttributes fa;
-  hipError_t e = hipFuncGetAttributes(&fa, kernel);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          160 * 1024 - (int)fa.sharedSizeBytes);
-  if (e == hipSuccess) done = true;
-  return e;
-}
 }  // namespace ccm
 
 extern "C" hipError_t ccm_launch_knn(const float* ts, int64_t ld, int L, const int* lib_ids,
@@ -559,8 +549,8 @@ extern "C" hipError_t ccm_launch_knn(const float* ts, int64_t ld, int L, const i
                                      const uint8_t* cand_mask, int* nbr_idx, float* nbr_w,
                                      float* nbr_d2, hipStream_t stream) {
   if (n_lib == 0) return hipSuccess;
-  static bool attr = false;
-  hipError_t e = ccm::allow_lds((const void*)ccm::knn_table_kernel, attr);
+  static std::atomic<uint64_t> attr{0};
+  hipError_t e = ccm::allow_lds_once((const void*)ccm::knn_table_kernel, attr);
   if (e != hipSuccess) return e;
   size_t lds = (size_t)(L + ccm::kPad) * sizeof(float) + (cand_mask ? (size_t)L : 0);
   hipLaunchKernelGGL(ccm::knn_table_kernel, dim3(n_lib), dim3(ccm::kKnnThreads), lds, stream, ts, ld,
@@ -573,8 +563,8 @@ extern "C" hipError_t ccm_launch_simplex(const float* ts, int64_t ld, int L, con
                                          int* optE, float* rho_E, double* rho64,
                                          hipStream_t stream) {
   if (n == 0) return hipSuccess;
-  static bool attr = false;
-  hipError_t e = ccm::allow_lds((const void*)ccm::simplex_kernel, attr);
+  static std::atomic<uint64_t> attr{0};
+  hipError_t e = ccm::allow_lds_once((const void*)ccm::simplex_kernel, attr);
   if (e != hipSuccess) return e;
   size_t lds = (size_t)(L + ccm::kPad) * sizeof(float);
   hipLaunchKernelGGL(ccm::simplex_kernel, dim3(n, 3), dim3(ccm::kSimplexThreads), lds, stream, ts,

@@ -3,7 +3,30 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 namespace ccm {
+
+// Raise a kernel's dynamic LDS limit to `bytes` (or, with bytes = 0, to all of the CU's
+// 160 KB left beside its static LDS) once per device: the attribute belongs to the device
+// the call is made on, so `done` keeps one bit per device id (ids below 64).
+inline hipError_t allow_lds_once(const void* kernel, std::atomic<uint64_t>& done,
+                                 size_t bytes = 0) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const uint64_t bit = dev >= 0 && dev < 64 ? (uint64_t)1 << dev : 0;
+  if (bit && (done.load(std::memory_order_acquire) & bit)) return hipSuccess;
+  if (bytes == 0) {
+    hipFuncAttributes fa;
+    e = hipFuncGetAttributes(&fa, kernel);
+    if (e != hipSuccess) return e;
+    bytes = 160 * 1024 - fa.sharedSizeBytes;
+  }
+  e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess && bit) done.fetch_or(bit, std::memory_order_acq_rel);
+  return e;
+}
 
 constexpr int kWave = 64;
 constexpr int kEMax = 20;
