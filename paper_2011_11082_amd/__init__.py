@@ -284,6 +284,38 @@ def ccm_convergence(ts: torch.Tensor, lib_ids, lib_E, masks, tau: int = 1, tgt0:
     return rho.reshape(n_lib, n_samp, -1)
 
 
+def ccm_matrix(ts: torch.Tensor, E_min: int = 1, E_max: int = E_MAX, tau: int = 1,
+               block: int = 512, precision: int = PRECISION_FP32, per_target_E: bool = False,
+               mode: int = MODE_LOO, out: Optional[torch.Tensor] = None):
+    """The whole N x N causal matrix of an L x N panel (Sec. III-B, Alg. 1 and Alg. 2):
+    phase 1 (optE of every series, E_min..E_max, Tp = 1, leave-one-out or the half split),
+    then blocks of `block` libraries, each a table call and a cross-map call against every
+    series.  rho[i][j] = cross-map skill of library i for target j (row = library).  With
+    per_target_E, target j is read through every library's table at j's own optE (the
+    paper's form; FP32 only); otherwise at the library's optE.  Returns (rho [N][N], optE)."""
+    ts, _, L = _panel(ts)
+    N = int(ts.shape[1])
+    ids = torch.arange(N, dtype=torch.int32, device=ts.device)
+    optE, _ = simplex_optE(ts, ids, E_min, E_max, tau, 1, mode)
+    if out is None:
+        out = torch.empty((N, N), dtype=torch.float32, device=ts.device)
+    elif out.shape != (N, N) or out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 [N][N] tensor")
+    if per_target_E and precision != PRECISION_FP32:
+        raise ValueError("the per-target-E form is FP32")
+    k_max = E_max + 1
+    for b0 in range(0, N, block):
+        b1 = min(N, b0 + block)
+        if per_target_E:
+            idx, w, _ = knn_all_E(ts, ids[b0:b1], E_min, E_max - E_min + 1, tau, k_max)
+            out[b0:b1] = crossmap_rho_target_E(ts, idx, w, b1 - b0, optE, E_lo=E_min, tau=tau)
+        else:
+            idx, w, _ = knn(ts, ids[b0:b1], optE[b0:b1], tau, 0, k_max, want_d2=False)
+            out[b0:b1] = crossmap_rho(ts, idx, w, optE[b0:b1], tau, precision=precision)
+        del idx, w
+    return out, optE
+
+
 def crossmap_rho_backward(ts, lib_ts, nbr_idx, nbr_w, lib_E, pair_lib, pair_tgt, grad_rho,
                           tau: int = 1, grad_ts=None, grad_lib=None):
     """Adjoint of sum_p grad_rho[p] * rho[pair_lib[p], pair_tgt[p]] with fixed neighbour sets.
