@@ -143,6 +143,8 @@ def main():
                     help="skip the per-target-E form (optE of every series + all-E tables)")
     ap.add_argument("--no-long-series", action="store_true",
                     help="skip the step at the paper's recording lengths (L = 3,780 and 8,528)")
+    ap.add_argument("--no-full-matrix", action="store_true",
+                    help="skip the whole N x N matrices of the 1,024- and 8,192-series workloads")
     ap.add_argument("--profile-steps", action="store_true",
                     help="no timing extras (for runs under rocprofv3)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -426,6 +428,32 @@ def main():
                 f"BF16 {eb0.elapsed_time(eb1):.1f})")
             del ts2, i2, w2, r2, rb
         res["long_series"] = long_res
+
+    # The whole N x N matrix (phase 1 over every series, then blocks of 512 libraries) of the
+    # 1,024-series rate network (L = 1,450) and the 8,192-series filtered-Poisson panel
+    # (L = 1,600), one timed call each after a warm-up; the latter in both cross-map forms.
+    if not args.no_full_matrix and not args.profile_steps:
+        fm = []
+        for name, precs in (("ratenet1024", (ccm.PRECISION_FP32,)),
+                            ("poisson8192", (ccm.PRECISION_FP32, ccm.PRECISION_BF16))):
+            wl3 = synth.make(name)
+            ts3 = torch.as_tensor(wl3.panel, device=dev)
+            N3 = int(ts3.shape[1])
+            for prec in precs:
+                for rep in range(2):   # one warm-up, one timed
+                    e0, e1 = ev(), ev()
+                    e0.record()
+                    r3, _ = ccm.ccm_matrix(ts3, 1, wl3.E_max, block=512, precision=prec)
+                    e1.record()
+                    torch.cuda.synchronize()
+                t3 = e0.elapsed_time(e1)
+                fm.append({"workload": name, "N": N3, "L": int(ts3.shape[0]),
+                           "precision": "bf16" if prec == ccm.PRECISION_BF16 else "fp32",
+                           "ms": round(t3, 2), "rate": round(N3 * N3 / (t3 * 1e-3), 1)})
+                log(f"full matrix {name} {fm[-1]['precision']}: {N3}x{N3} in {t3:.1f} ms")
+                del r3
+            del ts3
+        res["full_matrix"] = fm
 
     if not args.no_cpu_baseline and not args.profile_steps:
         log("timing the CPU oracle on a bounded sample")
