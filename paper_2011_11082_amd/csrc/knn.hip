@@ -67,12 +67,12 @@ __device__ __forceinline__ void offer_chunk(uint64_t cand, uint64_t& key, uint64
   while (m) {
     const int src = __ffsll((unsigned long long)m) - 1;
     const uint64_t kv = readlane(cand, src);
-    if (ballot(key == kv) == 0) {
+    m &= (~0ull << src) << 1;
+    if (ballot(key == kv) == 0) {   // a key met again leaves the list and its k-th as they are
       list_insert(key, kv);
       thr = readlane(key, k1);
+      m &= ballot(cand < thr);
     }
-    m &= (~0ull << src) << 1;
-    m &= ballot(cand < thr);
   }
 }
 
