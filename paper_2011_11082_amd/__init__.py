@@ -293,16 +293,19 @@ def ccm_matrix(ts: torch.Tensor, E_min: int = 1, E_max: int = E_MAX, tau: int = 
     series.  rho[i][j] = cross-map skill of library i for target j (row = library).  With
     per_target_E, target j is read through every library's table at j's own optE (the
     paper's form; FP32 only); otherwise at the library's optE.  Returns (rho [N][N], optE)."""
+    if per_target_E and precision != PRECISION_FP32:
+        raise ValueError("the per-target-E form is FP32")
+    if block < 1:
+        raise ValueError("block must be >= 1")
     ts, _, L = _panel(ts)
     N = int(ts.shape[1])
+    if out is not None and (tuple(out.shape) != (N, N) or out.dtype != torch.float32
+                            or not out.is_contiguous() or out.device != ts.device):
+        raise ValueError("out must be a contiguous float32 [N][N] tensor on the panel's device")
     ids = torch.arange(N, dtype=torch.int32, device=ts.device)
     optE, _ = simplex_optE(ts, ids, E_min, E_max, tau, 1, mode)
     if out is None:
         out = torch.empty((N, N), dtype=torch.float32, device=ts.device)
-    elif out.shape != (N, N) or out.dtype != torch.float32 or not out.is_contiguous():
-        raise ValueError("out must be a contiguous float32 [N][N] tensor")
-    if per_target_E and precision != PRECISION_FP32:
-        raise ValueError("the per-target-E form is FP32")
     k_max = E_max + 1
     for b0 in range(0, N, block):
         b1 = min(N, b0 + block)

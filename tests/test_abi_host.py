@@ -5,6 +5,7 @@ import os
 import re
 
 import pytest
+import torch
 
 import paper_2011_11082_amd as ccm
 
@@ -150,3 +151,12 @@ def test_knn_subset_requires_a_mask():
     # no libraries: nothing to do
     assert lib.ccm_knn_subset(fake, 8, 100, fake, fake, 0, 1, 0, 21, _null(), fake, fake, _null(),
                               _null(), 0, _null()) == ccm.CCM_OK
+
+
+def test_matrix_argument_errors_before_device_work():
+    # rejected before any device call (a CPU tensor never reaches the library)
+    x = torch.zeros((100, 8), dtype=torch.float32)
+    with pytest.raises(ValueError):
+        ccm.ccm_matrix(x, per_target_E=True, precision=ccm.PRECISION_BF16)
+    with pytest.raises(ValueError):
+        ccm.ccm_matrix(x, block=0)

@@ -1,8 +1,8 @@
 """The whole N x N causal matrix through ccm_matrix (phase 1, then blocks of libraries, each
 a table call and a cross-map call against every series), against the oracle on the 64-map
 coupled logistic network: optE as the oracle's (near-ties aside), every row whose library
-E matches within 1e-5, in both the library-E and the per-target-E forms, and the same
-matrix bit for bit whatever the block size."""
+E matches within 1e-5 (5e-3 in the BF16 form), in the library-E and the per-target-E forms,
+and the same matrix bit for bit whatever the block size."""
 import sys
 
 import numpy as np
@@ -68,3 +68,10 @@ def test_matrix_logistic64_both_forms(ccm):
     d = np.nanmax(np.abs(rtg - rho_t[:, cols]))
     print(f"matrix per-target E: |drho| max {d:.3e} over {len(cols)} columns")
     assert d < RHO_TOL
+    _say("ccm_matrix logistic64, BF16 form")
+    rb, _ = ccm.ccm_matrix(Y, 1, 10, block=64, precision=ccm.PRECISION_BF16)
+    rbg = rb.cpu().numpy()[rows].astype(np.float64)
+    assert np.array_equal(np.isnan(rbg), np.isnan(rho_o))
+    d = np.nanmax(np.abs(rbg - rho_o))
+    print(f"matrix BF16: |drho| max {d:.3e}")
+    assert d < 5e-3
