@@ -183,6 +183,48 @@ __device__ __forceinline__ double list_weight64(const float* x, int t, int nb, i
   return u;
 }
 
+// Sum over each 32-lane half (lanes 0..31 and 32..63), returned in every lane of that half:
+// the steps of lanes32_sum run in all four rows of 16 at once, so the upper half's sum is the
+// same sequence of operations on its own lanes.
+__device__ __forceinline__ double halves32_sum(double v) {
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  v += dpp_f64<0x124>(v);
+  v += dpp_f64<0x128>(v);
+  auto rl = [&](int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+  };
+  const double lo = rl(0) + rl(16);
+  const double hi = rl(32) + rl(48);
+  return lane_id() < 32 ? lo : hi;
+}
+
+// Simplex weights of two finished lists at once: list a of E in lanes 0..E, list b of E + 1
+// in lanes 32..33 + E (lane 32 + j holds its j-th neighbour).  Each half forms its own
+// weights exactly as list_weight64 does for one list.
+__device__ __forceinline__ double pair_weight64(const float* x, int t, int nb, int E, int tau,
+                                                double& usum) {
+  const int lane = lane_id();
+  const bool up = lane >= 32;
+  const int El = up ? E + 1 : E;
+  const bool in = (lane & 31) <= El && nb >= 0;
+  double dd = 0.0;
+  if (in)
+    for (int e = 0; e < El; ++e) {
+      double df = (double)x[t - e * tau] - (double)x[nb - e * tau];
+      dd += df * df;
+    }
+  const double d = sqrt(dd);
+  const double d1a = __hiloint2double(readlane(__double2hiint(d), 0), readlane(__double2loint(d), 0));
+  const double d1b = __hiloint2double(readlane(__double2hiint(d), 32), readlane(__double2loint(d), 32));
+  const double d1 = up ? d1b : d1a;
+  double u = 0.0;
+  if (in) u = d1 > 0.0 ? exp(-d / d1) : (d == 0.0 ? 1.0 : 0.0);
+  usum = halves32_sum(u);
+  return u;
+}
+
 constexpr int kKnnThreads = 1024;
 
 // The scan of one query at a compile-time E: every candidate chunk's lag reads are issued
@@ -420,17 +462,29 @@ __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, 
       }
     }
     const float obs = x[t + Tp];
+    // the lists of E and E + 1 are finished together: the second moves to lanes 32..63
+    static_assert(NG % 2 == 0, "lists are finished in pairs");
 #pragma unroll
-    for (int g = 0; g < NG; ++g) {
-      const int E = ELO + g;
-      if (E >= E_lo && E <= E_hi && t >= qbase + (E - 1) * tau) {
-        const int li = lane <= E ? key_idx(key[g]) : -1;
+    for (int g = 0; g < NG; g += 2) {
+      const int Ea = ELO + g;
+      const bool acta = Ea >= E_lo && Ea <= E_hi && t >= qbase + (Ea - 1) * tau;
+      const bool actb = Ea + 1 >= E_lo && Ea + 1 <= E_hi && t >= qbase + Ea * tau;
+      if (acta || actb) {
+        const bool up = lane >= 32;
+        const uint32_t blo = (uint32_t)__shfl_xor((int)(uint32_t)key[g + 1], 32);
+        const uint32_t bhi = (uint32_t)__shfl_xor((int)(uint32_t)(key[g + 1] >> 32), 32);
+        const uint64_t kk = up ? (((uint64_t)bhi << 32) | blo) : key[g];
+        const int El = up ? Ea + 1 : Ea;
+        const bool act = up ? actb : acta;
+        const int li = (act && (lane & 31) <= El) ? key_idx(kk) : -1;
         double usum;
-        double u = list_weight64(x, t, li, E, tau, E + 1, usum);
-        double f = (lane <= E && li >= 0) ? (double)x[li + Tp] : 0.0;
-        double pred = lanes32_sum(u * f) / usum;
-        if (lane == g) {
-          double o = obs, p = pred;
+        double u = pair_weight64(x, t, li, Ea, tau, usum);
+        double f = ((lane & 31) <= El && li >= 0) ? (double)x[li + Tp] : 0.0;
+        double pred = halves32_sum(u * f) / usum;
+        const double pb = __hiloint2double(readlane(__double2hiint(pred), 32),
+                                           readlane(__double2loint(pred), 32));
+        if ((lane == g && acta) || (lane == g + 1 && actb)) {
+          double o = obs, p = lane == g ? pred : pb;
           m_o += o;
           m_oo += o * o;
           m_p += p;
