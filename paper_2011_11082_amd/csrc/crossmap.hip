@@ -20,7 +20,7 @@
 //     table row so that at step j query t prefers a neighbour with s = t + j (mod 4),
 //     which keeps the four rows of a pass in distinct quarters whenever it can.
 //     The order of the k products only changes FP32 rounding.
-//   * Moments sum(yhat), sum(yhat^2), sum(y*yhat) are kept in FP32 for 16 blocks and folded
+//   * Moments sum(yhat), sum(yhat^2), sum(y*yhat) are kept in FP32 for 32 blocks and folded
 //     into FP64; sum(y), sum(y^2) over each library's query range come from per-tile FP64
 //     column sums.  rho is formed in FP64.
 //   * Waves of every workgroup visit libraries in the same order (heaviest first), so the
@@ -334,8 +334,8 @@ __device__ __forceinline__ void load_all(const uint32_t* bo, const float* bw, in
   }
 }
 
-// One library against the tile; FP32 moment sums (16 rows per lane) are folded into FP64
-// every 16 blocks.  The workspace holds spare blocks after the last library, so the load of
+// One library against the tile; FP32 moment sums (32 rows per lane) are folded into FP64
+// every 32 blocks.  The workspace holds spare blocks after the last library, so the load of
 // block b + 1 is always in bounds.
 template <int K, int TJ>
 __device__ __forceinline__ void gather_library(const char* smem, const uint32_t* __restrict__ po,
@@ -350,7 +350,7 @@ __device__ __forceinline__ void gather_library(const char* smem, const uint32_t*
   load_all<K, TJ>(bo, bw, lane, e);
   int b = b0;
   while (b < nblk) {
-    const int bend = b + 16 < nblk ? b + 16 : nblk;
+    const int bend = b + 32 < nblk ? b + 32 : nblk;
     for (; b < bend; ++b) {
       bo += bstride;
       bw += bstride;
