@@ -20,7 +20,8 @@
 //   Kernel 3 (first): one workgroup per library builds the transposed neighbour relation
 //   (for each time s, the table entries whose neighbour is s, in table order), the position
 //   of every entry in it, the weights in that order, and an m-major copy of the table.
-//   Kernel 1: one workgroup per pair recomputes yhat and the FP64 Pearson pieces and stores
+//   Kernel 1: one workgroup per pair reads its target column once (into LDS, and a
+//   contiguous copy for kernel 2), recomputes yhat and the FP64 Pearson pieces and stores
 //   H, Gy.  Kernel 2: one thread per (pair, t) turns wbar into distance coefficients
 //   (distances recomputed in FP64 from the library series), written m-major and in the
 //   transposed order.  Kernel 4: one thread per (pair, s) gathers everything that lands on
@@ -56,8 +57,9 @@ __global__ __launch_bounds__(kBwThreads) void bw_pair_kernel(
     const float* __restrict__ nbr_w, const int* __restrict__ lib_E, int n_lib, int k_max, int tau,
     const int* __restrict__ pair_lib, const int* __restrict__ pair_tgt,
     const float* __restrict__ grad_rho, float* __restrict__ yhat, float* __restrict__ H,
-    float* __restrict__ Gy, int* __restrict__ pair_ok) {
+    float* __restrict__ Gy, int* __restrict__ pair_ok, float* __restrict__ ycol) {
   __shared__ double red[kBwThreads / kWave];
+  extern __shared__ float yl[];   // the pair's target column, [L]
   const int p = blockIdx.x;
   const int i = pair_lib[p];
   const int j = pair_tgt[p];
@@ -75,6 +77,15 @@ __global__ __launch_bounds__(kBwThreads) void bw_pair_kernel(
     if (threadIdx.x == 0) pair_ok[p] = 0;
     return;
   }
+  // the target column, read once from the panel: LDS for this kernel, a contiguous copy
+  // in the workspace for the coefficient kernel
+  float* yc = ycol + (size_t)p * L;
+  for (int t = threadIdx.x; t < L; t += blockDim.x) {
+    const float v = ts[(int64_t)t * ld + j];
+    yl[t] = v;
+    yc[t] = v;
+  }
+  __syncthreads();
   double sy = 0.0, sp = 0.0;
   for (int t = threadIdx.x; t < L; t += blockDim.x) {
     float v = 0.0f;
@@ -82,8 +93,8 @@ __global__ __launch_bounds__(kBwThreads) void bw_pair_kernel(
       const int* ri = nbr_idx + ((size_t)i * L + t) * k_max;
       const float* rw = nbr_w + ((size_t)i * L + t) * k_max;
       for (int m = 0; m < k; ++m)
-        if (ri[m] >= 0) v = fmaf(rw[m], ts[(int64_t)ri[m] * ld + j], v);   // -1: padding
-      sy += ts[(int64_t)t * ld + j];
+        if (ri[m] >= 0) v = fmaf(rw[m], yl[ri[m]], v);   // -1: padding
+      sy += yl[t];
       sp += v;
     }
     yh[t] = v;
@@ -93,7 +104,7 @@ __global__ __launch_bounds__(kBwThreads) void bw_pair_kernel(
   const double pbar = block_sum(sp, red) / n;
   double a = 0.0, b = 0.0, c = 0.0, ay = 0.0, bp = 0.0;
   for (int t = lo + threadIdx.x; t < L; t += blockDim.x) {
-    const double y = ts[(int64_t)t * ld + j];
+    const double y = yl[t];
     const double q = yh[t];
     a += (y - ybar) * (y - ybar);
     b += (q - pbar) * (q - pbar);
@@ -113,7 +124,7 @@ __global__ __launch_bounds__(kBwThreads) void bw_pair_kernel(
   for (int t = threadIdx.x; t < L; t += blockDim.x) {
     double h = 0.0, gy = 0.0;
     if (good && t >= lo) {
-      const double dy = (double)ts[(int64_t)t * ld + j] - ybar;
+      const double dy = (double)yl[t] - ybar;
       const double dq = (double)yh[t] - pbar;
       h = g * (dy / sab - rho * dq / b);
       gy = g * (dq / sab - rho * dy / a);
@@ -132,7 +143,7 @@ __global__ __launch_bounds__(256) void bw_coef_kernel(
     const int* __restrict__ nbr_idx, const int* __restrict__ lib_E, int k_max, int tau,
     const int* __restrict__ pair_lib, const int* __restrict__ pair_tgt, int n_pairs,
     const float* __restrict__ H, const int* __restrict__ pair_ok, const int* __restrict__ csr_pos,
-    float* __restrict__ com, float* __restrict__ coT) {
+    const float* __restrict__ ycol, float* __restrict__ com, float* __restrict__ coT) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= (int64_t)n_pairs * L) return;
   const int p = (int)(g / L);
@@ -148,6 +159,7 @@ __global__ __launch_bounds__(256) void bw_coef_kernel(
   }
   const int* pos = csr_pos + ((size_t)i * L + t) * k_max;
   float* cT = coT + (size_t)p * L * k_max;
+  const float* yc = ycol + (size_t)p * L;   // the pair's target column
   const int j = pair_tgt[p];
   const float* x = lib_ts + (size_t)i * L;
   const int* ri = nbr_idx + ((size_t)i * L + t) * k_max;
@@ -170,7 +182,7 @@ __global__ __launch_bounds__(256) void bw_coef_kernel(
       dd += df * df;
     }
     d[m] = sqrt(dd);
-    wb[m] = h * (double)ts[(int64_t)nb * ld + j];
+    wb[m] = h * (double)yc[nb];
   }
   const double d1 = d[0];
   double S = 0.0;
@@ -373,13 +385,13 @@ __global__ __launch_bounds__(kWave) void bw_reduce_kernel(
 static size_t up256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 extern "C" size_t ccm_backward_ws_bytes(int L, int n_lib, int n_pairs, int k_max) {
-  // yhat, H, Gy, tc, lc: [P][L] floats; coefficients twice: [P][k_max][L] and [P][L k_max]
+  // yhat, H, Gy, tc, lc, the target columns: [P][L] floats; coefficients twice: [P][k_max][L] and [P][L k_max]
   // floats; pair_ok: [P] ints; per library: CSR offsets [L + 1], entries, positions, weights
   // and the m-major table copy, [L k_max] each
   const size_t a = up256((size_t)n_pairs * L * 4);
   const size_t c = up256((size_t)n_pairs * L * k_max * 4);
   const size_t t = up256((size_t)n_lib * L * k_max * 4);
-  return 5 * a + 2 * c + up256((size_t)n_pairs * 4) + up256((size_t)n_lib * (L + 1) * 4) + 4 * t;
+  return 6 * a + 2 * c + up256((size_t)n_pairs * 4) + up256((size_t)n_lib * (L + 1) * 4) + 4 * t;
 }
 
 extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, const float* lib_ts,
@@ -398,9 +410,10 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
   float* lc = (float*)(base + 4 * a);
   const size_t c = up256((size_t)n_pairs * L * k_max * 4);
   const size_t tb = up256((size_t)n_lib * L * k_max * 4);
-  float* com = (float*)(base + 5 * a);
-  float* coT = (float*)(base + 5 * a + c);
-  char* after_coef = base + 5 * a + 2 * c;
+  float* ycol = (float*)(base + 5 * a);
+  float* com = (float*)(base + 6 * a);
+  float* coT = (float*)(base + 6 * a + c);
+  char* after_coef = base + 6 * a + 2 * c;
   int* pair_ok = (int*)after_coef;
   int* csr_off = (int*)(after_coef + up256((size_t)n_pairs * 4));
   int* csr_ent = (int*)((char*)csr_off + up256((size_t)n_lib * (L + 1) * 4));
@@ -413,13 +426,16 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
   hipLaunchKernelGGL(ccm::bw_transpose_kernel, dim3(n_lib), dim3(ccm::kTrThreads),
                      (size_t)(L + 1 + ccm::kTrThreads) * sizeof(int), stream, nbr_idx, nbr_w, lib_E,
                      L, k_max, tau, csr_off, csr_ent, csr_pos, csr_w, idx_m);
-  hipLaunchKernelGGL(ccm::bw_pair_kernel, dim3(n_pairs), dim3(ccm::kBwThreads), 0, stream, ts, ld, L,
+  static std::atomic<uint64_t> attr_pair{0};
+  e = ccm::allow_lds_once((const void*)ccm::bw_pair_kernel, attr_pair, (size_t)L * sizeof(float));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(ccm::bw_pair_kernel, dim3(n_pairs), dim3(ccm::kBwThreads), (size_t)L * sizeof(float), stream, ts, ld, L,
                      nbr_idx, nbr_w, lib_E, n_lib, k_max, tau, pair_lib, pair_tgt, grad_rho, yhat, H,
-                     Gy, pair_ok);
+                     Gy, pair_ok, ycol);
   const int64_t rows = (int64_t)n_pairs * L;
   hipLaunchKernelGGL(ccm::bw_coef_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, stream,
                      ts, ld, L, lib_ts, nbr_idx, lib_E, k_max, tau, pair_lib, pair_tgt, n_pairs, H,
-                     pair_ok, csr_pos, com, coT);
+                     pair_ok, csr_pos, ycol, com, coT);
   hipLaunchKernelGGL(ccm::bw_scatter_kernel, dim3((L + 255) / 256, n_pairs), dim3(256), 0, stream, ts,
                      ld, L, lib_ts, lib_E, k_max, tau, pair_lib, n_pairs, H, Gy, pair_ok, com, coT,
                      csr_off, csr_ent, csr_w, idx_m, tc, lc);
