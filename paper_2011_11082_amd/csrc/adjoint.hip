@@ -291,22 +291,31 @@ __global__ __launch_bounds__(256) void bw_scatter_kernel(
     const int* __restrict__ pair_ok, const float* __restrict__ com, const float* __restrict__ coT,
     const int* __restrict__ csr_off, const int* __restrict__ csr_ent, const float* __restrict__ csr_w,
     const int* __restrict__ idx_m, float* __restrict__ tc, float* __restrict__ lc) {
+  extern __shared__ float sm[];   // the library series [L], then the pair's H [L]
   const int p = blockIdx.y;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= L) return;
   float* tco = tc + (size_t)p * L;
   float* lco = lc + (size_t)p * L;
-  if (!pair_ok[p]) {
-    tco[s] = 0.0f;
-    lco[s] = 0.0f;
+  if (!pair_ok[p]) {   // the whole workgroup
+    if (s < L) {
+      tco[s] = 0.0f;
+      lco[s] = 0.0f;
+    }
     return;
   }
   const int i = pair_lib[p];
   const int E = lib_E[i];
   const int k = E + 1;
   const int lo = (E - 1) * tau;
-  const float* x = lib_ts + (size_t)i * L;
-  const float* hp = H + (size_t)p * L;
+  // the series and H are read at scattered times: from LDS
+  float* x = sm;
+  float* hp = sm + L;
+  for (int q = threadIdx.x; q < L; q += blockDim.x) {
+    x[q] = lib_ts[(size_t)i * L + q];
+    hp[q] = H[(size_t)p * L + q];
+  }
+  __syncthreads();
+  if (s >= L) return;
   const float* cm = com + (size_t)p * k_max * L;       // [m][t]
   const float* cT = coT + (size_t)p * L * k_max;       // transposed order
   const int* im = idx_m + (size_t)i * k_max * L;       // [m][t]
@@ -436,7 +445,11 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
   hipLaunchKernelGGL(ccm::bw_coef_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, stream,
                      ts, ld, L, lib_ts, nbr_idx, lib_E, k_max, tau, pair_lib, pair_tgt, n_pairs, H,
                      pair_ok, csr_pos, ycol, com, coT);
-  hipLaunchKernelGGL(ccm::bw_scatter_kernel, dim3((L + 255) / 256, n_pairs), dim3(256), 0, stream, ts,
+  static std::atomic<uint64_t> attr_scatter{0};
+  e = ccm::allow_lds_once((const void*)ccm::bw_scatter_kernel, attr_scatter, (size_t)2 * L * sizeof(float));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(ccm::bw_scatter_kernel, dim3((L + 255) / 256, n_pairs), dim3(256),
+                     (size_t)2 * L * sizeof(float), stream, ts,
                      ld, L, lib_ts, lib_E, k_max, tau, pair_lib, n_pairs, H, Gy, pair_ok, com, coT,
                      csr_off, csr_ent, csr_w, idx_m, tc, lc);
   hipLaunchKernelGGL(ccm::bw_reduce_kernel, dim3((L + ccm::kWave - 1) / ccm::kWave, ccm::kRedHash),
