@@ -74,7 +74,7 @@ typedef int32_t ccm_status;
  *   ids [n]          series (columns of ts) to embed.
  *   emb [n][L-(E-1)tau][E]  output; emb[i][r][e] = ts[(r + (E-1)tau - e tau) * ld + ids[i]].
  * Errors: EINVAL for null pointers or n < 0; ERANGE if E outside [1, CCM_E_MAX], tau < 1
- * or (E-1) tau >= L.  ids out of [0, ld) are the caller's responsibility.
+ * or (E-1) tau >= L.  A series id outside [0, ld) gets NaN in every element of its block.
  */
 ccm_status ccm_embed(const float* ts, int64_t ld, int32_t L, const int32_t* ids, int32_t n,
                      int32_t E, int32_t tau, float* emb, void* stream);
@@ -98,7 +98,8 @@ ccm_status ccm_embed(const float* ts, int64_t ld, int32_t L, const int32_t* ids,
  *     nbr_d2   (nullable) the FP32 d^2 of each neighbour.
  *   Rows t outside the query set and slots beyond E + 1 are padding: idx = -1, w = 0,
  *   d2 = +inf.  A library whose E is out of [1, CCM_E_MAX], has E + 1 > k_max, or has
- *   fewer than E + 2 points gets padding in every row (and NaN rho downstream).
+ *   fewer than E + 2 points, or whose series id is outside [0, ld), gets padding in every row
+ *   (and NaN rho downstream).
  * Errors: EINVAL (nulls, n_lib < 0, k_max < 2 or > CCM_K_MAX, Tp < 0); ERANGE (L or tau).
  * Workspace: none (ws may be NULL).
  */
@@ -132,7 +133,8 @@ ccm_status ccm_knn_subset(const float* ts, int64_t ld, int32_t L, const int32_t*
  *   query excluded.  mode CCM_MODE_HALF: candidates from the first half [0, L/2) and queries
  *   from the second half, each half embedded on its own, no exclusion.
  *   optE [n]                 smallest E reaching the largest non-NaN rho_E (E_min if all NaN).
- *   rho_E [n][E_max-E_min+1] (nullable) the skills; NaN where a variance vanishes.
+ *   rho_E [n][E_max-E_min+1] (nullable) the skills; NaN where a variance vanishes, and in
+ *                            every E for a series id outside [0, ld) (whose optE is E_min).
  * Errors: EINVAL (nulls, bad mode, Tp < 0); ERANGE (E range, or too few points for
  * k = E_max + 1 candidates).  Workspace: ccm_workspace_size(CCM_OP_SIMPLEX, ...).
  */

@@ -289,17 +289,18 @@ __global__ __launch_bounds__(kKnnThreads) void knn_table_kernel(const float* __r
   __shared__ int n_adm;
   const int lib = blockIdx.x;
   const int sid = lib_ids[lib];
+  const bool sid_ok = sid >= 0 && sid < ld;   // a series outside the panel gets padding
   const int E = __builtin_amdgcn_readfirstlane(lib_E[lib]);
   const int k = E + 1;
   const int lo = (E - 1) * tau;           // first point
   const int hi = L - 1 - Tp;              // last point with a future
   if (threadIdx.x == 0) n_adm = 0;
   for (int t = threadIdx.x; t < L + kPad; t += blockDim.x)
-    xbuf[t] = t < kPad ? 0.0f : ts[(int64_t)(t - kPad) * ld + sid];
+    xbuf[t] = t < kPad || !sid_ok ? 0.0f : ts[(int64_t)(t - kPad) * ld + sid];
   if (mb)
     for (int t = threadIdx.x; t < L; t += blockDim.x) mb[t] = cand_mask[(size_t)lib * L + t];
   __syncthreads();
-  bool ok = E >= 1 && E <= kEMax && k <= k_max && (hi - lo + 1) - 1 >= k;
+  bool ok = sid_ok && E >= 1 && E <= kEMax && k <= k_max && (hi - lo + 1) - 1 >= k;
   if (mb && ok) {   // enough marked candidates for every query (one may be the query itself)
     int c = 0;
     for (int t = lo + threadIdx.x; t <= hi; t += blockDim.x) c += mb[t] != 0;
@@ -516,6 +517,11 @@ __global__ __launch_bounds__(kSimplexThreads) void simplex_kernel(
   const int E_hi = EHI < E_max ? EHI : E_max;
   if (E_lo > E_hi) return;  // whole workgroup: group outside [E_min, E_max]
   const int sid = ids[blockIdx.x];
+  if (sid < 0 || sid >= ld) {   // a series outside the panel: NaN skills, so optE = E_min
+    if ((int)threadIdx.x >= E_lo - 1 && (int)threadIdx.x < E_hi)
+      rho64[(size_t)blockIdx.x * kEMax + threadIdx.x] = __builtin_nan("");
+    return;
+  }
   for (int t = threadIdx.x; t < L + kPad; t += blockDim.x)
     xbuf[t] = t < kPad ? 0.0f : ts[(int64_t)(t - kPad) * ld + sid];
   __syncthreads();
@@ -587,7 +593,8 @@ __global__ void embed_kernel(const float* __restrict__ ts, int64_t ld, int L,
     const int r = (int)(re % nr);
     const int i = (int)(re / nr);
     const int t = r + (E - 1) * tau - e * tau;
-    emb[g] = ts[(int64_t)t * ld + ids[i]];
+    const int sid = ids[i];
+    emb[g] = sid >= 0 && sid < ld ? ts[(int64_t)t * ld + sid] : __builtin_nanf("");
   }
 }
 

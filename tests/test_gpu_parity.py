@@ -82,6 +82,27 @@ def test_knn_invalid_library_gets_padding(ccm):
     assert np.all(idx.cpu().numpy() == -1) and np.all(w.cpu().numpy() == 0)
 
 
+def test_series_ids_outside_the_panel(ccm):
+    # ids outside [0, ld) are never read: padding tables, NaN skills (optE = E_min), NaN
+    # embeddings; the valid ids of the same call are unaffected
+    rng = np.random.default_rng(6)
+    ts = rng.standard_normal((80, 2)).astype(np.float32)
+    _say("series ids outside the panel: knn, simplex, embed")
+    idx, w, d2 = ccm.knn(_cuda(ts), [1, -1, 2, 0], [3, 3, 3, 3], k_max=4)
+    idx, w = idx.cpu().numpy(), w.cpu().numpy()
+    assert np.all(idx[1:3] == -1) and np.all(w[1:3] == 0)
+    ref_idx, ref_w, _ = ccm.knn(_cuda(ts), [1, 0], [3, 3], k_max=4)
+    assert np.array_equal(idx[[0, 3]], ref_idx.cpu().numpy())
+    assert np.array_equal(w[[0, 3]], ref_w.cpu().numpy())
+    optE, rho = ccm.simplex_optE(_cuda(ts), [1, 7, -3], 2, 12, 1, 1)
+    optE, rho = optE.cpu().numpy(), rho.cpu().numpy()
+    assert list(optE[1:]) == [2, 2] and np.all(np.isnan(rho[1:]))
+    ref_optE, ref_rho = ccm.simplex_optE(_cuda(ts), [1], 2, 12, 1, 1)
+    assert optE[0] == ref_optE.item() and np.array_equal(rho[0], ref_rho.cpu().numpy()[0])
+    emb = ccm.embed(_cuda(ts), [0, 2, -1], 4, 1).cpu().numpy()
+    assert np.array_equal(emb[0], O.embed(ts[:, 0], 4, 1)) and np.all(np.isnan(emb[1:]))
+
+
 def test_knn_bit_exact_logistic64(ccm):
     w = synth.make("logistic64")
     ts = w.panel
