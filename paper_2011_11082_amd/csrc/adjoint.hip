@@ -436,7 +436,7 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
                      (size_t)(L + 1 + ccm::kTrThreads) * sizeof(int), stream, nbr_idx, nbr_w, lib_E,
                      L, k_max, tau, csr_off, csr_ent, csr_pos, csr_w, idx_m);
   static std::atomic<uint64_t> attr_pair{0};
-  e = ccm::allow_lds_once((const void*)ccm::bw_pair_kernel, attr_pair, (size_t)L * sizeof(float));
+  e = ccm::allow_lds_once((const void*)ccm::bw_pair_kernel, attr_pair);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(ccm::bw_pair_kernel, dim3(n_pairs), dim3(ccm::kBwThreads), (size_t)L * sizeof(float), stream, ts, ld, L,
                      nbr_idx, nbr_w, lib_E, n_lib, k_max, tau, pair_lib, pair_tgt, grad_rho, yhat, H,
@@ -446,7 +446,7 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
                      ts, ld, L, lib_ts, nbr_idx, lib_E, k_max, tau, pair_lib, pair_tgt, n_pairs, H,
                      pair_ok, csr_pos, ycol, com, coT);
   static std::atomic<uint64_t> attr_scatter{0};
-  e = ccm::allow_lds_once((const void*)ccm::bw_scatter_kernel, attr_scatter, (size_t)2 * L * sizeof(float));
+  e = ccm::allow_lds_once((const void*)ccm::bw_scatter_kernel, attr_scatter);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(ccm::bw_scatter_kernel, dim3((L + 255) / 256, n_pairs), dim3(256),
                      (size_t)2 * L * sizeof(float), stream, ts,

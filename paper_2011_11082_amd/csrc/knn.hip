@@ -601,9 +601,8 @@ __global__ void embed_kernel(const float* __restrict__ ts, int64_t ld, int L,
 }  // namespace ccm
 
 // ---- launchers (called from the C ABI) ----------------------------------------------
-namespace ccm {
-// The series copy (and mask) of a long series exceeds the default 64 KB of dynamic LDS.
-}  // namespace ccm
+// The series copy (and mask) of a long series exceeds the default 64 KB of dynamic LDS, so
+// each kernel is first allowed all of the LDS its static use leaves.
 
 extern "C" hipError_t ccm_launch_knn(const float* ts, int64_t ld, int L, const int* lib_ids,
                                      const int* lib_E, int n_lib, int tau, int Tp, int k_max,

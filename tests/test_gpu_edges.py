@@ -2,7 +2,8 @@
 (bit-exact, every E and several lags), lag tau = 2 in the cross-map (both precisions), the
 largest series the FP32 LDS tile holds (L = 2475), series beyond it (L = 3000: the tile is
 read from a global copy, in both the library-E and the per-target-E forms), long series in
-the table and optE kernels (sampled query rows), and empty inputs."""
+the table and optE kernels (sampled query rows), the largest length the ABI accepts in the
+tables, both cross-map forms and the adjoint, and empty inputs."""
 import sys
 
 import numpy as np
@@ -156,6 +157,62 @@ def test_long_series_tables_and_optE(ccm):
     oE, oR, _ = O.simplex_optE(ts3, [0, 1], 1, 4, 1, 1)
     assert np.array_equal(optE.cpu().numpy(), oE)
     assert np.abs(rho_E.cpu().numpy() - oR).max() < 1e-5
+
+
+def test_maximum_length_crossmap_and_adjoint(ccm):
+    # L = 16384, the largest the ABI accepts: tables at E = 3 and E = 20 on sampled rows
+    # against the oracle; the cross-map (FP32 from the global 32-target tile, and BF16) of
+    # an exactly periodic library with distinct phase states, whose targets of the same
+    # period are predicted exactly (every neighbour has d = 0 and the same phase, so
+    # rho = 1) and whose constant target gives NaN; and the adjoint's invariances
+    # (rho unchanged by y -> a y + b and x -> a x + b) on the noisy library's tables.
+    import torch
+
+    L = 16384
+    rng = np.random.default_rng(47)
+    x = (np.sin(0.031 * np.arange(L)) + 0.3 * rng.standard_normal(L)).astype(np.float32)
+    P = 37
+    cols = [x, synth.periodic(P, L, rng)]
+    cols += [synth.periodic(P, L, rng) for _ in range(38)]      # targets 2..39
+    cols += [np.full(L, 0.5, np.float32), np.roll(x, 5)]        # 40: constant, 41: noisy
+    ts = np.stack(cols, axis=1).astype(np.float32)
+    Y = _cuda(ts)
+    libs, lib_E = [0, 0, 1], [3, 20, 3]
+    _say("knn L=16384 E=3 and E=20, sampled rows")
+    idx, wt, d2 = ccm.knn(Y, libs, lib_E, k_max=21)
+    idx_h, wt_h, d2_h = idx.cpu().numpy(), wt.cpu().numpy(), d2.cpu().numpy()
+    for r in (0, 1):
+        E = lib_E[r]
+        Q, C, _ = O.point_sets(L, E, 1, 0)
+        q = np.concatenate([Q[:3], Q[::523], Q[-3:]])
+        D2 = O.sqdist_fp32(x, q, C, E, 1)
+        idx_o, d2_o = O.select_knn(D2, q, C, E + 1, True)
+        w_o = O.weights_rows_fp64(x, q, idx_o, E, 1)
+        assert np.array_equal(idx_h[r][q][:, : E + 1], idx_o), f"E={E} indices"
+        assert np.array_equal(d2_h[r][q][:, : E + 1], d2_o), f"E={E} d2"
+        assert np.abs(wt_h[r][q][:, : E + 1].astype(np.float64) - w_o).max() < 2e-6
+        assert np.all(idx_h[r][q][:, E + 1:] == -1) and np.all(idx_h[r][: E - 1] == -1)
+    _say("crossmap L=16384 periodic library, 40 targets (FP32 global tile, BF16)")
+    sub = (idx[2:3].contiguous(), wt[2:3].contiguous())
+    for prec, tol in ((ccm.PRECISION_FP32, 1e-6), (ccm.PRECISION_BF16, 5e-3)):
+        rho = ccm.crossmap_rho(Y, sub[0], sub[1], [3], tgt0=2, n_tgt=39,
+                               precision=prec).cpu().numpy()[0]
+        assert np.abs(rho[:38] - 1.0).max() < tol, (prec, np.abs(rho[:38] - 1.0).max())
+        assert np.isnan(rho[38])
+    _say("adjoint L=16384, 2 pairs")
+    X = torch.as_tensor(np.ascontiguousarray(ts[:, libs].T)).cuda()
+    y = ts[:, 41].astype(np.float64)
+    for r in (0, 1):
+        gt, gl = ccm.crossmap_rho_backward(Y, X, idx, wt, lib_E, [r], [41], torch.ones(1))
+        gy = gt[:, 41].double().cpu().numpy()
+        gx = gl[r].double().cpu().numpy()
+        assert np.all(np.isfinite(gy)) and np.all(np.isfinite(gx))
+        assert np.abs(gy).sum() > 0 and np.abs(gx).sum() > 0
+        for g, v in ((gy, y), (gx, x.astype(np.float64))):
+            r1 = abs(g.sum()) / np.abs(g).sum()
+            r2 = abs((v * g).sum()) / np.abs(v * g).sum()
+            print(f"E={lib_E[r]}: invariance residuals {r1:.2e} {r2:.2e}")
+            assert r1 <= 2e-5 and r2 <= 2e-5
 
 
 def test_empty_inputs(ccm):
