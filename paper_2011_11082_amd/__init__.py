@@ -113,6 +113,10 @@ def _panel(ts: torch.Tensor):
     _dev(ts, "ts", torch.float32)
     if ts.dim() != 2 or ts.stride(1) != 1:
         raise ValueError("ts must be a 2-D [L][N] panel with unit stride along N")
+    if ts.device.index is not None and ts.device.index != torch.cuda.current_device():
+        # kernels launch on the current device and its current stream
+        raise ValueError(f"ts is on {ts.device}, the current device is cuda:"
+                         f"{torch.cuda.current_device()} (use torch.cuda.device(...))")
     return ts, int(ts.stride(0)), int(ts.shape[0])
 
 

@@ -274,7 +274,9 @@ __device__ __forceinline__ void knn_query(const float* x, const uint8_t* mb, int
 // Neighbour tables at each library's own E (one launch for every E).
 // grid.x = n_lib, block = 1024 (16 waves, one query each at a time); LDS: the series.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kKnnThreads) void knn_table_kernel(const float* __restrict__ ts, int64_t ld,
+// At most 64 VGPRs (8 waves per SIMD), so two 16-wave workgroups share a CU: 2.96 -> 2.70 ms
+// for 512 tables at L = 1600, 40.1 -> 35.4 ms for 10,240, with no spill.
+__global__ __launch_bounds__(kKnnThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void knn_table_kernel(const float* __restrict__ ts, int64_t ld,
                                                         int L, const int* __restrict__ lib_ids,
                                                         const int* __restrict__ lib_E, int tau,
                                                         int Tp, int k_max,
