@@ -138,6 +138,61 @@ __global__ __launch_bounds__(kBwThreads) void bw_pair_kernel(
 // coef = dbar_m / d_m (0 for zero distances), one thread per (pair, t), written twice: m-major
 // (com[p][m][t], read by the query side) and in the library's transposed order (coT[p][q] at
 // q = pos[t][m], read by the neighbour side).
+// One row's coefficients at a compile-time k = E + 1, so the per-neighbour FP64 distances
+// and kernel values stay in registers (the weighted target h y(n_m) is re-read).
+__device__ __forceinline__ double coef_wb(const float* yc, int nb, double h) {
+  return nb < 0 ? 0.0 : h * (double)yc[nb];
+}
+template <int K>
+__device__ __forceinline__ void coef_row(const float* x, const float* yc, const int* ri,
+                                         const int* pos, int t, int tau, double h, int k_max,
+                                         int L, float* cm_out, float* cT) {
+  constexpr int E = K - 1;
+  double d[K], u[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    const int nb = ri[m];
+    if (nb < 0) {   // padding entry: weight 0, no distance
+      d[m] = INFINITY;
+      continue;
+    }
+    double dd = 0.0;
+#pragma unroll 1
+    for (int e = 0; e < E; ++e) {
+      const double df = (double)x[t - e * tau] - (double)x[nb - e * tau];
+      dd += df * df;
+    }
+    d[m] = sqrt(dd);
+  }
+  const double d1 = d[0];
+  double S = 0.0;
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    u[m] = ri[m] < 0 ? 0.0 : d1 > 0.0 ? exp(-d[m] / d1) : (d[m] == 0.0 ? 1.0 : 0.0);
+    S += u[m];
+  }
+  double sw = 0.0;
+#pragma unroll
+  for (int m = 0; m < K; ++m) sw += coef_wb(yc, ri[m], h) * (u[m] / S);
+  double dbar1 = 0.0;
+#pragma unroll
+  for (int m = 1; m < K; ++m) {
+    double cm = 0.0;
+    if (ri[m] >= 0 && d1 > 0.0 && d[m] > 0.0) {
+      const double ub = (coef_wb(yc, ri[m], h) - sw) / S;
+      const double db = -ub * u[m] / d1;
+      dbar1 += ub * u[m] * d[m] / (d1 * d1);
+      cm = db / d[m];
+    }
+    cm_out[(size_t)m * L] = (float)cm;
+    if (ri[m] >= 0 && ri[m] < L) cT[pos[m]] = (float)cm;
+  }
+  for (int m = K; m < k_max; ++m) cm_out[(size_t)m * L] = 0.0f;
+  const float c0 = d1 > 0.0 ? (float)(dbar1 / d1) : 0.0f;
+  cm_out[0] = c0;
+  if (ri[0] >= 0 && ri[0] < L) cT[pos[0]] = c0;
+}
+
 __global__ __launch_bounds__(256) void bw_coef_kernel(
     const float* __restrict__ ts, int64_t ld, int L, const float* __restrict__ lib_ts,
     const int* __restrict__ nbr_idx, const int* __restrict__ lib_E, int k_max, int tau,
@@ -151,7 +206,6 @@ __global__ __launch_bounds__(256) void bw_coef_kernel(
   float* cm_out = com + (size_t)p * k_max * L + t;     // stride L between m
   const int i = pair_lib[p];
   const int E = pair_ok[p] ? lib_E[i] : 0;
-  const int k = E + 1;
   const int lo = (E - 1) * tau;
   if (!pair_ok[p] || t < lo) {
     for (int m = 0; m < k_max; ++m) cm_out[(size_t)m * L] = 0.0f;
@@ -160,55 +214,22 @@ __global__ __launch_bounds__(256) void bw_coef_kernel(
   const int* pos = csr_pos + ((size_t)i * L + t) * k_max;
   float* cT = coT + (size_t)p * L * k_max;
   const float* yc = ycol + (size_t)p * L;   // the pair's target column
-  const int j = pair_tgt[p];
   const float* x = lib_ts + (size_t)i * L;
   const int* ri = nbr_idx + ((size_t)i * L + t) * k_max;
   const double h = H[(size_t)p * L + t];
-  double d[kKMax], u[kKMax], wb[kKMax];
   if (ri[0] < 0) {   // a row of padding only (a subsampled table): no contribution
     for (int m = 0; m < k_max; ++m) cm_out[(size_t)m * L] = 0.0f;
     return;
   }
-  for (int m = 0; m < k; ++m) {
-    const int nb = ri[m];
-    if (nb < 0) {   // padding entry: weight 0, no distance
-      d[m] = INFINITY;
-      wb[m] = 0.0;
-      continue;
-    }
-    double dd = 0.0;
-    for (int e = 0; e < E; ++e) {
-      const double df = (double)x[t - e * tau] - (double)x[nb - e * tau];
-      dd += df * df;
-    }
-    d[m] = sqrt(dd);
-    wb[m] = h * (double)yc[nb];
+  switch (E) {   // pair_ok guarantees 1 <= E <= 20 and E + 1 <= k_max
+#define CCM_K(EE) \
+  case EE: coef_row<EE + 1>(x, yc, ri, pos, t, tau, h, k_max, L, cm_out, cT); break;
+    CCM_K(1) CCM_K(2) CCM_K(3) CCM_K(4) CCM_K(5) CCM_K(6) CCM_K(7) CCM_K(8) CCM_K(9) CCM_K(10)
+    CCM_K(11) CCM_K(12) CCM_K(13) CCM_K(14) CCM_K(15) CCM_K(16) CCM_K(17) CCM_K(18) CCM_K(19)
+    CCM_K(20)
+#undef CCM_K
+    default: break;
   }
-  const double d1 = d[0];
-  double S = 0.0;
-  for (int m = 0; m < k; ++m) {
-    u[m] = ri[m] < 0 ? 0.0 : d1 > 0.0 ? exp(-d[m] / d1) : (d[m] == 0.0 ? 1.0 : 0.0);
-    S += u[m];
-  }
-  double sw = 0.0;
-  for (int m = 0; m < k; ++m) sw += wb[m] * (u[m] / S);
-  double dbar1 = 0.0;
-  for (int m = 0; m < k_max; ++m) {
-    double cm = 0.0;
-    if (m >= 1 && m < k && ri[m] >= 0 && d1 > 0.0 && d[m] > 0.0) {
-      const double ub = (wb[m] - sw) / S;
-      const double db = -ub * u[m] / d1;
-      dbar1 += ub * u[m] * d[m] / (d1 * d1);
-      cm = db / d[m];
-    }
-    if (m >= 1) {
-      cm_out[(size_t)m * L] = (float)cm;
-      if (m < k && ri[m] >= 0 && ri[m] < L) cT[pos[m]] = (float)cm;
-    }
-  }
-  const float c0 = d1 > 0.0 ? (float)(dbar1 / d1) : 0.0f;
-  cm_out[0] = c0;
-  if (ri[0] >= 0 && ri[0] < L) cT[pos[0]] = c0;
 }
 
 // Contributions of pair p to time s: target (tc) and library (lc).  One thread per (p, s).
