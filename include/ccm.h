@@ -25,7 +25,9 @@
  *   - Time indices are int32; values are float32; correlation moments are float64.
  *   - A point of an E-dimensional embedding is labelled by its newest coordinate:
  *     point t = (x(t), x(t - tau), ..., x(t - (E-1) tau)), t >= (E-1) tau.
- *   - Inputs must be finite.
+ *   - Inputs must be finite.  ccm_set_check_finite(1) turns on a debug mode in which each
+ *     entry point first checks the floating-point inputs it reads and returns CCM_EINVAL
+ *     for a non-finite value (that mode synchronises the stream).
  *   - 1 <= E <= CCM_E_MAX, tau >= 1, L <= CCM_L_MAX.
  */
 #ifndef CCM_H
@@ -226,6 +228,18 @@ ccm_status ccm_crossmap_rho_backward(const float* ts, int64_t ld, int32_t L, con
  */
 ccm_status ccm_workspace_size(int32_t op, int32_t L, int32_t n_lib, int32_t n_tgt,
                               int32_t k_max, size_t* bytes);
+
+/*
+ * ccm_set_check_finite -- debug mode for the convention that inputs are finite (host call,
+ * process-wide, off by default).  With on != 0, every later call first checks, on its
+ * stream, the series columns it reads (ids, library ids, targets, or the pairs' target
+ * columns), the tables' weights, and the backward's library series and upstream gradients,
+ * waits for that check (a host synchronisation, which the calls otherwise never make),
+ * and returns CCM_EINVAL ("non-finite input value") without launching the operation if a
+ * value is NaN or infinite.  With on = 0 nothing is checked: non-finite inputs then give
+ * unspecified (typically NaN) outputs, never a fault.  Always returns CCM_OK.
+ */
+ccm_status ccm_set_check_finite(int32_t on);
 
 /* Static text of a status code. */
 const char* ccm_status_string(ccm_status s);

@@ -30,7 +30,8 @@ PRECISION_FP32, PRECISION_BF16 = 0, 1
 
 EXPORTED = (
     "ccm_embed", "ccm_knn", "ccm_knn_subset", "ccm_simplex_optE", "ccm_crossmap_rho",
-    "ccm_crossmap_rho_backward", "ccm_crossmap_rho_target_E", "ccm_workspace_size", "ccm_status_string", "ccm_last_error", "ccm_version",
+    "ccm_crossmap_rho_backward", "ccm_crossmap_rho_target_E", "ccm_workspace_size",
+    "ccm_set_check_finite", "ccm_status_string", "ccm_last_error", "ccm_version",
 )
 
 
@@ -72,6 +73,7 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
         "ccm_crossmap_rho_target_E": [_P, _I64, _I32, _P, _P, _I32, _I32, _I32, _I32, _I32, _P,
                                       _I32, _I32, _P, _P, _P, _SZ, _P],
         "ccm_workspace_size": [_I32, _I32, _I32, _I32, _I32, ctypes.POINTER(_SZ)],
+        "ccm_set_check_finite": [_I32],
         "ccm_status_string": [_I32],
         "ccm_last_error": [],
         "ccm_version": [],
@@ -126,6 +128,12 @@ def _i32(t, device) -> torch.Tensor:
     else:
         t = torch.as_tensor(t, dtype=torch.int32, device=device)
     return t.contiguous()
+
+
+def set_check_finite(on: bool) -> None:
+    """Debug mode (process-wide): every call first checks that the values it reads are
+    finite, synchronising its stream, and raises CCMError (CCM_EINVAL) if one is not."""
+    _check(load_library().ccm_set_check_finite(1 if on else 0))
 
 
 def workspace_size(op: int, L: int, n_lib: int, n_tgt: int, k_max: int) -> int:

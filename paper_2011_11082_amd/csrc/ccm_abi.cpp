@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
 #include <string>
 
 #include "../../include/ccm.h"
@@ -134,6 +135,80 @@ Bf16Ws bf16_ws(int L, int n_lib, int n_tgt) {
   return w;
 }
 
+// ---- debug mode: finiteness of the inputs (off by default) ------------------------------
+std::atomic<int> g_check_finite{0};
+
+// Sets *bad when a value of the listed series (columns `cols`, or col0 .. col0 + n_cols - 1
+// when cols is NULL; ids outside [0, ld) are skipped) is not finite.
+__global__ void finite_cols_kernel(const float* ts, int64_t ld, int L, const int* cols, int col0,
+                                   int n_cols, int* bad) {
+  const int64_t total = (int64_t)L * n_cols;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int ci = (int)(g % n_cols);
+    const int64_t t = g / n_cols;
+    const int c = cols ? cols[ci] : col0 + ci;
+    if (c >= 0 && c < ld && !isfinite(ts[t * ld + c])) *bad = 1;
+  }
+}
+
+__global__ void finite_flat_kernel(const float* a, int64_t n, int* bad) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * blockDim.x)
+    if (!isfinite(a[g])) *bad = 1;
+}
+
+struct FiniteSpec {
+  const float* ts = nullptr;   // series columns of the panel
+  int64_t ld = 0;
+  int L = 0;
+  const int* cols = nullptr;
+  int col0 = 0, n_cols = 0;
+  const float* flat[3] = {nullptr, nullptr, nullptr};   // whole arrays
+  int64_t flat_n[3] = {0, 0, 0};
+};
+
+unsigned grid_for(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+// In debug mode, runs the checks on `stream`, waits for them and returns EINVAL if a value
+// is not finite (CCM_OK otherwise, and at once when debug mode is off).
+ccm_status check_finite(const char* fn, const FiniteSpec& f, hipStream_t stream) {
+  if (!g_check_finite.load(std::memory_order_relaxed)) return CCM_OK;
+  int* bad = nullptr;
+  hipError_t e = hipMalloc((void**)&bad, sizeof(int));
+  if (e != hipSuccess) return device_status(fn, e);
+  int h = 0;
+  e = hipMemcpyAsync(bad, &h, sizeof(int), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess && f.ts && f.n_cols > 0 && f.L > 0) {
+    hipLaunchKernelGGL(finite_cols_kernel, dim3(grid_for((int64_t)f.L * f.n_cols)), dim3(256), 0,
+                       stream, f.ts, f.ld, f.L, f.cols, f.col0, f.n_cols, bad);
+    e = hipGetLastError();
+  }
+  for (int a = 0; a < 3 && e == hipSuccess; ++a)
+    if (f.flat[a] && f.flat_n[a] > 0) {
+      hipLaunchKernelGGL(finite_flat_kernel, dim3(grid_for(f.flat_n[a])), dim3(256), 0, stream,
+                         f.flat[a], f.flat_n[a], bad);
+      e = hipGetLastError();
+    }
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, bad, sizeof(int), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  const hipError_t ef = hipFree(bad);
+  if (e == hipSuccess) e = ef;
+  if (e != hipSuccess) return device_status(fn, e);
+  return h ? fail(CCM_EINVAL, fn, "non-finite input value (debug check)") : CCM_OK;
+}
+
+FiniteSpec targets_and_weights(const float* ts, int64_t ld, int L, int tgt0, int n_tgt,
+                               const float* nbr_w, int64_t n_w) {
+  FiniteSpec f;
+  f.ts = ts; f.ld = ld; f.L = L; f.col0 = tgt0; f.n_cols = n_tgt;
+  f.flat[0] = nbr_w; f.flat_n[0] = n_w;
+  return f;
+}
+
 bool check_series(const char* fn, ccm_status* st, const float* ts, int64_t ld, int32_t L,
                   int32_t tau) {
   if (!ts) { *st = fail(CCM_EINVAL, fn, "ts is NULL"); return false; }
@@ -148,6 +223,11 @@ bool check_series(const char* fn, ccm_status* st, const float* ts, int64_t ld, i
 extern "C" {
 
 const char* ccm_version(void) { return "ccm-gfx950 0.1"; }
+
+ccm_status ccm_set_check_finite(int32_t on) {
+  g_check_finite.store(on ? 1 : 0, std::memory_order_relaxed);
+  return CCM_OK;
+}
 
 const char* ccm_last_error(void) { return g_last_error.c_str(); }
 
@@ -202,6 +282,9 @@ ccm_status ccm_embed(const float* ts, int64_t ld, int32_t L, const int32_t* ids,
   if (E < 1 || E > CCM_E_MAX) return fail(CCM_ERANGE, fn, "E outside [1, CCM_E_MAX]");
   if ((int64_t)(E - 1) * tau >= L) return fail(CCM_ERANGE, fn, "(E-1)*tau >= L");
   if (n > 0 && (!ids || !emb)) return fail(CCM_EINVAL, fn, "ids or emb is NULL");
+  FiniteSpec f;
+  f.ts = ts; f.ld = ld; f.L = L; f.cols = ids; f.n_cols = n;
+  if ((st = check_finite(fn, f, (hipStream_t)stream)) != CCM_OK) return st;
   return device_status(fn, ccm_launch_embed(ts, ld, L, ids, n, E, tau, emb, (hipStream_t)stream));
 }
 
@@ -217,6 +300,9 @@ ccm_status knn_common(const char* fn, const float* ts, int64_t ld, int32_t L,
     return fail(CCM_EINVAL, fn, "NULL array argument");
   if (k_max < 2 || k_max > CCM_K_MAX) return fail(CCM_EINVAL, fn, "k_max outside [2, CCM_K_MAX]");
   if (Tp < 0 || Tp >= L) return fail(CCM_EINVAL, fn, "Tp outside [0, L)");
+  FiniteSpec f;
+  f.ts = ts; f.ld = ld; f.L = L; f.cols = lib_ids; f.n_cols = n_lib;
+  if ((st = check_finite(fn, f, (hipStream_t)stream)) != CCM_OK) return st;
   return device_status(fn, ccm_launch_knn(ts, ld, L, lib_ids, lib_E, n_lib, tau, Tp, k_max,
                                           cand_mask, nbr_idx, nbr_w, nbr_d2, (hipStream_t)stream));
 }
@@ -266,6 +352,9 @@ ccm_status ccm_simplex_optE(const float* ts, int64_t ld, int32_t L, const int32_
   if (n == 0) return CCM_OK;
   const size_t need = align_up((size_t)n * CCM_E_MAX * sizeof(double));
   if (!ws || ws_bytes < need) return fail(CCM_EWORKSPACE, fn, "workspace too small");
+  FiniteSpec f;
+  f.ts = ts; f.ld = ld; f.L = L; f.cols = ids; f.n_cols = n;
+  if ((st = check_finite(fn, f, (hipStream_t)stream)) != CCM_OK) return st;
   return device_status(fn, ccm_launch_simplex(ts, ld, L, ids, n, E_min, E_max, tau, Tp, mode, optE,
                                               rho_E, (double*)ws, (hipStream_t)stream));
 }
@@ -287,6 +376,10 @@ ccm_status ccm_crossmap_rho(const float* ts, int64_t ld, int32_t L, const int32_
     CrossmapWs w = fp32_ws(L, n_lib, k_max, n_tgt);
     if (n_lib == 0 || n_tgt == 0) return CCM_OK;
     if (!ws || ws_bytes < w.total) return fail(CCM_EWORKSPACE, fn, "workspace too small");
+    if ((st = check_finite(fn, targets_and_weights(ts, ld, L, tgt0, n_tgt, nbr_w,
+                                                   (int64_t)n_lib * L * k_max),
+                           (hipStream_t)stream)) != CCM_OK)
+      return st;
     char* base = (char*)ws;
     return device_status(
         fn, ccm_launch_crossmap_fp32(ts, ld, L, tau, tgt0, n_tgt, nbr_idx, nbr_w, lib_E, n_lib, k_max,
@@ -299,6 +392,10 @@ ccm_status ccm_crossmap_rho(const float* ts, int64_t ld, int32_t L, const int32_
     Bf16Ws w = bf16_ws(L, n_lib, n_tgt);
     if (n_lib == 0 || n_tgt == 0) return CCM_OK;
     if (!ws || ws_bytes < w.total) return fail(CCM_EWORKSPACE, fn, "workspace too small");
+    if ((st = check_finite(fn, targets_and_weights(ts, ld, L, tgt0, n_tgt, nbr_w,
+                                                   (int64_t)n_lib * L * k_max),
+                           (hipStream_t)stream)) != CCM_OK)
+      return st;
     char* base = (char*)ws;
     return device_status(
         fn, ccm_launch_crossmap_bf16(ts, ld, L, tau, tgt0, n_tgt, nbr_idx, nbr_w, lib_E, n_lib, k_max,
@@ -332,6 +429,10 @@ ccm_status ccm_crossmap_rho_target_E(const float* ts, int64_t ld, int32_t L,
   const TargetEWs w = target_E_ws(L, n_E * n_lib, n_tgt, k_max);
   if (n_lib == 0 || n_tgt == 0) return CCM_OK;
   if (!ws || ws_bytes < w.total) return fail(CCM_EWORKSPACE, fn, "workspace too small");
+  if ((st = check_finite(fn, targets_and_weights(ts, ld, L, tgt0, n_tgt, nbr_w,
+                                                 (int64_t)n_E * n_lib * L * k_max),
+                         (hipStream_t)stream)) != CCM_OK)
+    return st;
   char* base = (char*)ws;
   return device_status(
       fn, ccm_launch_crossmap_fp32_target_E(
@@ -360,6 +461,12 @@ ccm_status ccm_crossmap_rho_backward(const float* ts, int64_t ld, int32_t L, con
   if (!grad_ts && !grad_lib) return fail(CCM_EINVAL, fn, "both gradients are NULL");
   const size_t need = ccm_backward_ws_bytes(L, n_lib, n_pairs, k_max);
   if (!ws || ws_bytes < need) return fail(CCM_EWORKSPACE, fn, "workspace too small");
+  FiniteSpec f;
+  f.ts = ts; f.ld = ld; f.L = L; f.cols = pair_tgt; f.n_cols = n_pairs;
+  f.flat[0] = lib_ts; f.flat_n[0] = (int64_t)n_lib * L;
+  f.flat[1] = nbr_w; f.flat_n[1] = (int64_t)n_lib * L * k_max;
+  f.flat[2] = grad_rho; f.flat_n[2] = n_pairs;
+  if ((st = check_finite(fn, f, (hipStream_t)stream)) != CCM_OK) return st;
   return device_status(fn, ccm_launch_backward(ts, ld, L, lib_ts, nbr_idx, nbr_w, lib_E, n_lib,
                                                k_max, tau, pair_lib, pair_tgt, grad_rho, n_pairs,
                                                grad_ts, grad_lib, ws, (hipStream_t)stream));

@@ -41,6 +41,12 @@ def test_status_strings_and_version():
     assert lib.ccm_version().startswith(b"ccm-gfx950")
 
 
+def test_check_finite_switch_is_host_only():
+    lib = ccm.load_library()
+    assert lib.ccm_set_check_finite(1) == ccm.CCM_OK
+    assert lib.ccm_set_check_finite(0) == ccm.CCM_OK
+
+
 def test_workspace_size_host_only():
     n = ccm.workspace_size(ccm.OP_CROSSMAP_FP32, 1600, 512, 101729, 21)
     # blocked tables: 512 libraries x 100 blocks x 6 slots x 64 lanes x (4 + 4) bytes

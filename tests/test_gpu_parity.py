@@ -103,6 +103,46 @@ def test_series_ids_outside_the_panel(ccm):
     assert np.array_equal(emb[0], O.embed(ts[:, 0], 4, 1)) and np.all(np.isnan(emb[1:]))
 
 
+def test_debug_mode_rejects_non_finite_inputs(ccm):
+    # with the finiteness check on, a NaN or infinity in a series, target or weight that the
+    # call reads makes it fail with CCM_EINVAL before any work; values it does not read
+    # (other columns) are ignored
+    import torch
+
+    rng = np.random.default_rng(8)
+    ts = rng.standard_normal((100, 6)).astype(np.float32)
+    ts[40, 3] = np.nan
+    Y = _cuda(ts)
+    _say("debug mode: non-finite inputs")
+    ccm.set_check_finite(True)
+    try:
+        def rejected(fn, *a, **kw):
+            with pytest.raises(ccm.CCMError) as ei:
+                fn(*a, **kw)
+            assert ei.value.status == ccm.CCM_EINVAL and "non-finite" in str(ei.value)
+
+        idx, wt, _ = ccm.knn(Y, [0, 1], [2, 2], k_max=3)
+        rejected(ccm.knn, Y, [0, 3], [2, 2], k_max=3)
+        rejected(ccm.simplex_optE, Y, [3], 1, 3, 1, 1)
+        rejected(ccm.embed, Y, [1, 3], 2, 1)
+        ccm.crossmap_rho(Y, idx, wt, [2, 2], tgt0=4, n_tgt=2)
+        rejected(ccm.crossmap_rho, Y, idx, wt, [2, 2], tgt0=2, n_tgt=3)
+        rejected(ccm.crossmap_rho, Y, idx, wt, [2, 2], tgt0=2, n_tgt=3,
+                 precision=ccm.PRECISION_BF16)
+        wbad = wt.clone()
+        wbad[1, 10, 0] = float("inf")
+        rejected(ccm.crossmap_rho, Y, idx, wbad, [2, 2], tgt0=4, n_tgt=2)
+        X = torch.as_tensor(np.ascontiguousarray(ts[:, [0, 1]].T)).cuda()
+        ccm.crossmap_rho_backward(Y, X, idx, wt, [2, 2], [0], [5], torch.ones(1))
+        rejected(ccm.crossmap_rho_backward, Y, X, idx, wt, [2, 2], [0], [3], torch.ones(1))
+        rejected(ccm.crossmap_rho_backward, Y, X, idx, wt, [2, 2], [0], [5],
+                 torch.full((1,), float("nan")))
+    finally:
+        ccm.set_check_finite(False)
+    idx2, wt2, _ = ccm.knn(Y, [0, 1], [2, 2], k_max=3)
+    assert torch.equal(idx, idx2) and torch.equal(wt, wt2)
+
+
 def test_knn_bit_exact_logistic64(ccm):
     w = synth.make("logistic64")
     ts = w.panel
