@@ -2,7 +2,8 @@
 a table call and a cross-map call against every series), against the oracle on the 64-map
 coupled logistic network: optE as the oracle's (near-ties aside), every row whose library
 E matches within 1e-5 (5e-3 in the BF16 form), in the library-E and the per-target-E forms,
-and the same matrix bit for bit whatever the block size."""
+and the same matrix bit for bit whatever the block size; and with phase 1 by the paper's half
+split."""
 import sys
 
 import numpy as np
@@ -75,3 +76,29 @@ def test_matrix_logistic64_both_forms(ccm):
     d = np.nanmax(np.abs(rbg - rho_o))
     print(f"matrix BF16: |drho| max {d:.3e}")
     assert d < 5e-3
+
+
+def test_matrix_logistic64_half_split(ccm):
+    # phase 1 by the paper's half split (library half, target half) inside ccm_matrix; the
+    # cross-map rows then use each library's half-split E
+    import torch
+
+    w = synth.make("logistic64")
+    ts = w.panel
+    N = ts.shape[1]
+    Y = torch.as_tensor(ts).cuda()
+    _say("ccm_matrix logistic64, half-split phase 1, E=1..8")
+    rho, optE = ccm.ccm_matrix(Y, 1, 8, block=32, mode=ccm.MODE_HALF)
+    oE, oR, _ = O.simplex_optE(ts, np.arange(N), 1, 8, 1, 1, mode=O.MODE_HALF)
+    g = optE.cpu().numpy()
+    same = g == oE
+    for i in np.nonzero(~same)[0]:
+        r = np.sort(oR[i][~np.isnan(oR[i])])[::-1]
+        assert len(r) > 1 and r[0] - r[1] < 1e-6, f"optE differs at series {i}"
+    rows = np.nonzero(same)[0]
+    rho_o, _, _, _ = O.ccm_block(ts, rows, oE[rows], 1, 0, N, k_max=9)
+    rg = rho.cpu().numpy()[rows].astype(np.float64)
+    assert np.array_equal(np.isnan(rg), np.isnan(rho_o))
+    d = np.nanmax(np.abs(rg - rho_o))
+    print(f"matrix half split: |drho| max {d:.3e} over {len(rows)} rows")
+    assert d < RHO_TOL
