@@ -190,6 +190,26 @@ def test_optE_logistic64(ccm):
     _check_optE(optE.cpu().numpy(), rho.cpu().numpy(), oE, oR, "logistic64")
 
 
+def test_longer_horizons(ccm):
+    # Tp > 1: candidates need s + Tp <= L - 1 and predict Tp steps ahead, in the tables and
+    # in both phase-1 protocols
+    w = synth.make("logistic64")
+    ts = w.panel
+    ids = np.arange(8)
+    _say("knn Tp=3, logistic64 sample")
+    lib_E = np.array([1, 2, 3, 5, 8, 10, 13, 20], dtype=np.int32)
+    idx, wt, d2 = ccm.knn(_cuda(ts), ids, lib_E, Tp=3, k_max=21)
+    _check_tables(ts, ids, lib_E, 1, 3, 21, idx.cpu().numpy(), wt.cpu().numpy(),
+                  d2.cpu().numpy(), "Tp=3")
+    _say("simplex Tp=3 LOO E=1..10, Tp=2 HALF tau=2 E=2..6")
+    optE, rho = ccm.simplex_optE(_cuda(ts), ids, 1, 10, 1, 3, ccm.MODE_LOO)
+    oE, oR, _ = O.simplex_optE(ts, ids, 1, 10, 1, 3)
+    _check_optE(optE.cpu().numpy(), rho.cpu().numpy(), oE, oR, "Tp=3 LOO")
+    optE, rho = ccm.simplex_optE(_cuda(ts), ids, 2, 6, 2, 2, ccm.MODE_HALF)
+    oE, oR, _ = O.simplex_optE(ts, ids, 2, 6, 2, 2, O.MODE_HALF)
+    _check_optE(optE.cpu().numpy(), rho.cpu().numpy(), oE, oR, "Tp=2 HALF tau=2")
+
+
 def test_optE_ratenet_sample_and_half_mode(ccm):
     w = synth.make("ratenet1024")
     ts = w.panel
