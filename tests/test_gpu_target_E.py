@@ -58,6 +58,21 @@ def test_target_E_logistic64(ccm):
     _check_rho(rho, rho_o, "target-E logistic64")
 
 
+def test_target_E_tau2(ccm):
+    # lag tau = 2: each (library, E) table embeds with lags 0, 2, .., 2(E-1), and target j's
+    # prediction rows start at (E_j - 1) * 2
+    w = synth.make("logistic64")
+    ts = w.panel
+    lib_ids = np.array([1, 9, 30, 57], dtype=np.int32)
+    tgt_E = np.random.default_rng(32).integers(2, 9, size=40).astype(np.int32)
+    _say("target-E logistic64 tau=2, 4 libs x 40 targets, E 2..8")
+    idx, wt, _ = ccm.knn_all_E(_cuda(ts), lib_ids, 2, 7, tau=2, k_max=9)
+    rho = ccm.crossmap_rho_target_E(_cuda(ts), idx, wt, len(lib_ids), tgt_E, E_lo=2, tau=2,
+                                    tgt0=5, n_tgt=40).cpu().numpy()
+    rho_o = O.crossmap_rho_target_E(ts, lib_ids, tgt_E, 2, 5, 40, k_max=9)
+    _check_rho(rho, rho_o, "target-E tau=2")
+
+
 def test_target_E_ratenet_ragged_and_missing_E(ccm):
     w = synth.make("ratenet1024")
     ts = w.panel
