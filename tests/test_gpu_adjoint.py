@@ -147,3 +147,30 @@ def test_adjoint_subsampled_and_padded_tables(ccm):
         gt, gl = ccm.crossmap_rho_backward(Y, X, idx, wt, lib_E, [r], [21], torch.ones(1))
         _check_invariances(gt[:, 21].double().cpu().numpy(), gl[r].double().cpu().numpy(),
                            ts[:, 21].astype(np.float64), ts[:, libs[r]].astype(np.float64))
+
+
+def test_adjoint_tau2_against_oracle(ccm):
+    # lag tau = 2 through the whole adjoint (distances over lags 0, 2, .., the scatter of a
+    # point's lag coordinates back to the series), against the FP64 oracle gradient
+    import torch
+
+    w = synth.make("logistic64")
+    ts = w.panel
+    L, N = ts.shape
+    libs = np.array([2, 11, 40, 63], dtype=np.int32)
+    lib_E = np.array([2, 3, 4, 5], dtype=np.int32)
+    rng = np.random.default_rng(48)
+    pairs = np.stack([rng.integers(0, 4, 12), rng.integers(0, N, 12)], axis=1).astype(np.int32)
+    Y = torch.as_tensor(ts).cuda()
+    X = torch.as_tensor(np.ascontiguousarray(ts[:, libs].T)).cuda()
+    _say("adjoint tau=2, 4 libraries, 12 pairs")
+    idx, wt, _ = ccm.knn(Y, libs, lib_E, tau=2, k_max=6)
+    gt, gl = ccm.crossmap_rho_backward(Y, X, idx, wt, lib_E, pairs[:, 0], pairs[:, 1],
+                                       torch.ones(len(pairs)), tau=2)
+    idx_o, _, _ = O.knn(ts, libs, lib_E, 2, 0, 6)
+    assert np.array_equal(idx.cpu().numpy(), idx_o)
+    g_tgt, g_lib = O.crossmap_rho_grad(ts, libs, lib_E, idx_o, 2, pairs, np.ones(len(pairs)))
+    rt = _rel(gt.cpu().numpy().astype(np.float64), g_tgt)
+    rl = _rel(gl.cpu().numpy().astype(np.float64), g_lib)
+    print(f"adjoint tau=2 rel L2 error: targets {rt:.2e}, libraries {rl:.2e}")
+    assert rt < 1e-3 and rl < 1e-3
