@@ -65,6 +65,29 @@ def test_subsampled_tables_bit_exact(ccm):
         assert masks[r][n].all()
 
 
+def test_subsampled_tables_tau2_bit_exact(ccm):
+    # lag tau = 2 with a library subsample: candidates are marked points s >= (E-1) * 2
+    w = synth.make("logistic64")
+    ts = w.panel
+    L = ts.shape[0]
+    lib_ids, lib_E, masks = [], [], []
+    for sid, E in ((5, 3), (33, 6)):
+        for m in (E + 2, 60, 300):
+            lib_ids.append(sid)
+            lib_E.append(E)
+            masks.append(synth.library_samples(L, E, [m], 1, sid, tau=2)[0])
+    masks = np.array(masks)
+    _say("subsampled tables logistic64 tau=2, 6 rows")
+    idx, wt, d2 = ccm.knn(_cuda(ts), lib_ids, lib_E, tau=2, k_max=7, cand_mask=_cuda(masks))
+    idx, wt, d2 = idx.cpu().numpy(), wt.cpu().numpy(), d2.cpu().numpy()
+    idx_o, w_o, d2_o = O.knn(ts, lib_ids, lib_E, 2, 0, 7, cand_masks=masks)
+    bad = np.argwhere(idx != idx_o)
+    assert bad.size == 0, f"{len(bad)} index mismatches, first {bad[:3].tolist()}"
+    valid = idx_o >= 0
+    assert np.array_equal(d2[valid], d2_o[valid])
+    assert np.abs(wt.astype(np.float64) - w_o).max() < 2e-6
+
+
 def test_full_mask_equals_plain_tables_and_small_mask_pads(ccm):
     w = synth.make("ratenet1024")
     ts = _cuda(w.panel)
