@@ -314,8 +314,12 @@ __device__ __forceinline__ void gather_block(const char* smem, Slots<(K + 3) / 4
                                              const uint32_t* nbo, const float* nbw, int lane,
                                              uint32_t laneoff, int t, int L, Moments& m) {
   float4 acc, ya[2], yb[2];
+  // a wave issuing its row's reads and products runs ahead of waves in their moment
+  // updates (65.0 -> 61.1 ms on 512 x 101,729 at L = 1600, identical rho)
+  __builtin_amdgcn_s_setprio(1);
   pair_reads<0, K>(smem, e, laneoff, ya);
   gather_row_pipe<K, TJ>(smem, e, nbo, nbw, lane, laneoff, ya, yb, acc);
+  __builtin_amdgcn_s_setprio(0);
   t = t < L ? t : L - 1;
   const float4 yo = *(const float4*)(smem + laneoff + (uint32_t)t * Geo<TJ>::ROW);
   m.sp.x += acc.x; m.sp.y += acc.y; m.sp.z += acc.z; m.sp.w += acc.w;
