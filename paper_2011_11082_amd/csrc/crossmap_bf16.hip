@@ -233,6 +233,10 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
       const uint16_t* ap = Aw + (lane & 31) * kRS + 8 * (lane >> 5);
       const uint16_t* bp = Bb + (lane & 31) * kRS + 8 * (lane >> 5);
       bf16x8 fa[2], fb0[2], fb1[2];
+      // raised priority while the fragments and products of the stage issue, so waves in
+      // their MFMA phase run ahead of waves scattering or clearing entries (227 -> 222 ms on
+      // 512 x 101,729, identical rho)
+      __builtin_amdgcn_s_setprio(1);
       fa[0] = *(const bf16x8*)ap;
       fb0[0] = *(const bf16x8*)bp;
       fb1[0] = *(const bf16x8*)(bp + 32 * kRS);
@@ -249,6 +253,7 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
         acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[c], fb1[c], acc[0][1], 0, 0, 0);
         __builtin_amdgcn_sched_barrier(0);
       }
+      __builtin_amdgcn_s_setprio(0);
       // clear this wave's nonzeros again (after its own reads, in program order)
       for (int e = e0 + lane; e < e1; e += kWave) Aw[(eo[e] & 31) * kRS + ((eo[e] >> 7) & 63)] = 0;
     };
