@@ -459,3 +459,138 @@ def test_convergence_on_two_species():
     # the driver's library recovers the weakly coupled direction less well at every size
     back = O.ccm_convergence(ts, [0], [2], masks[None], 1, 1, 1, k_max=3)[0, :, 0]
     assert np.all(back.reshape(len(sizes), 8).mean(axis=1) < curve)
+
+
+# --- simplex skill at horizons Tp >= 1 (Sec. II-B; Alg. 1 phase 1) ------------------------
+def _brute_simplex_rho(xi, E, tau, Tp, half):
+    """Pure-Python simplex skill on an integer series, from the definition: embed, pick the
+    E + 1 nearest library points by exact integer d^2 then time index, forecast x(t + Tp) as
+    the weighted mean of the neighbours' own values Tp steps later, and correlate the
+    forecasts with what was observed (two-pass Pearson, NaN on a zero variance).
+    Leave-one-out: every point with a future is both query and candidate, the query itself
+    excluded.  Half split: candidates from the first half, queries from the second, each
+    point's window and future inside its own half."""
+    L = len(xi)
+    span = (E - 1) * tau
+    if half:
+        h = L // 2
+        lib = [s for s in range(L) if s - span >= 0 and s + Tp <= h - 1]
+        qry = [t for t in range(L) if t - span >= h and t + Tp <= L - 1]
+    else:
+        lib = [s for s in range(L) if s - span >= 0 and s + Tp <= L - 1]
+        qry = list(lib)
+    obs, pred = [], []
+    for t in qry:
+        near = sorted((sum((xi[t - e * tau] - xi[s - e * tau]) ** 2 for e in range(E)), s)
+                      for s in lib if half or s != t)[:E + 1]
+        d = [math.sqrt(c[0]) for c in near]
+        u = ([math.exp(-dk / d[0]) for dk in d] if d[0] > 0 else
+             [1.0 if dk == 0 else 0.0 for dk in d])
+        pred.append(sum(uk * xi[c[1] + Tp] for uk, c in zip(u, near)) / sum(u))
+        obs.append(float(xi[t + Tp]))
+    mo, mp = sum(obs) / len(obs), sum(pred) / len(pred)
+    so = sum((a - mo) ** 2 for a in obs)
+    sp = sum((b - mp) ** 2 for b in pred)
+    if so == 0 or sp == 0:
+        return float("nan")
+    return sum((a - mo) * (b - mp) for a, b in zip(obs, pred)) / math.sqrt(so * sp)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+@pytest.mark.parametrize("half", [False, True])
+def test_simplex_rho_matches_brute_force(seed, half):
+    rng = np.random.default_rng(100 + seed)
+    L = 44
+    # few distinct values: exact ties and zero distances in every list
+    xi = rng.integers(0, 6, size=L).tolist()
+    x = np.array(xi, dtype=np.float32)
+    mode = O.MODE_HALF if half else O.MODE_LOO
+    checked = 0
+    for Tp in (1, 2, 3):
+        for tau in (1, 2):
+            for E in (1, 2, 3, 4):
+                want = _brute_simplex_rho(xi, E, tau, Tp, half)
+                got = O.simplex_rho(x, E, tau, Tp, mode)
+                if math.isnan(want):
+                    assert math.isnan(got), (E, tau, Tp)
+                else:
+                    assert abs(got - want) < 1e-12, (E, tau, Tp, got, want)
+                    checked += 1
+    assert checked >= 20
+
+
+def test_simplex_rho_sees_the_horizon():
+    """Forecasting x(t+Tp) is not forecasting x(t): on a random integer series the skills
+    at Tp = 0, 1, 2 all differ, so a dropped or doubled +Tp cannot pass the brute force."""
+    rng = np.random.default_rng(7)
+    xi = rng.integers(0, 9, size=40).tolist()
+    x = np.array(xi, dtype=np.float32)
+    r = [O.simplex_rho(x, 2, 1, Tp) for Tp in (0, 1, 2)]
+    assert len({round(v, 9) for v in r}) == 3
+    for Tp, v in zip((1, 2), r[1:]):
+        assert abs(v - _brute_simplex_rho(xi, 2, 1, Tp, False)) < 1e-12
+
+
+def test_simplex_hand_worked_tp1():
+    with open(os.path.join(GOLDEN, "hand_worked_simplex_Tp1.json")) as f:
+        g = json.load(f)
+    env = {"exp": math.exp}
+    for name, mode in (("loo", O.MODE_LOO), ("half", O.MODE_HALF)):
+        blk = g[name]
+        x = np.array(blk["x"], dtype=np.float32)
+        Q, idx, w, d2 = O.knn_table(x, g["E"], g["tau"], g["Tp"], mode)
+        assert Q.tolist() == [row["t"] for row in blk["rows"]]
+        pred, obs = [], []
+        for r, row in enumerate(blk["rows"]):
+            assert idx[r].tolist() == row["nbr"], (name, row["t"])
+            want = [eval(expr, env) for expr in row["w"]]
+            np.testing.assert_allclose(w[r], want, rtol=0, atol=1e-15)
+            pred.append(eval(row["pred"], env))
+            obs.append(float(row["obs"]))
+        want_rho = np.corrcoef(obs, pred)[0, 1]
+        assert abs(O.simplex_rho(x, g["E"], g["tau"], g["Tp"], mode) - want_rho) < 1e-14, name
+
+
+def test_simplex_periodic_closed_form():
+    """x(t) = tab[t mod 5] with tab = (0, 1, 0, 2, 3): one lag cannot tell phase 0 from
+    phase 2 (both read 0; one step later they read 1 and 2, two steps later 0 and 3), two
+    lags can.  Once E resolves the phase the
+    nearest neighbours sit at distance 0 in the same phase and the zero-distance rule gives
+    an exact forecast at any horizon: rho_E = 1.  At E = 1 the forecast is not exact, so
+    optE >= 2 (which of the E >= 2, all 1 up to rounding, wins is left to rounding).  A
+    forecast of x(t) instead of x(t+Tp) would be exact at E = 1 already."""
+    tab = [0.0, 1.0, 0.0, 2.0, 3.0]
+    L = 120
+    x = np.array([tab[t % 5] for t in range(L)], dtype=np.float32)
+    for mode in (O.MODE_LOO, O.MODE_HALF):
+        for Tp in (1, 2):
+            assert O.simplex_rho(x, 1, 1, Tp, mode) < 0.99, (mode, Tp)
+            for E in (2, 3, 5):
+                assert abs(O.simplex_rho(x, E, 1, Tp, mode) - 1.0) < 1e-12, (mode, Tp, E)
+        optE, rho, nanf = O.simplex_optE(x[:, None], [0], 1, 6, 1, 1, mode)
+        assert optE[0] >= 2 and not nanf[0] and rho[0, 0] < 0.99
+        np.testing.assert_allclose(rho[0, 1:], 1.0, rtol=0, atol=1e-12)
+    # at Tp = 0 the one-lag forecast of x(t) itself is exact (the degenerate protocol)
+    assert abs(O.simplex_rho(x, 1, 1, 0) - 1.0) < 1e-12
+
+
+# --- the Pearson zero-variance rule -------------------------------------------------------
+def test_pearson_nan_threshold_boundary():
+    """A centred sum of squares counts as zero when it is at most 1e-10 of the raw sum of
+    squares.  a = 1 + delta * s with s = (+1, -1, ...) over n = 10 points has centred sum
+    n delta^2 and raw sum n (1 + delta^2): the boundary is delta^2 = 1e-10 / (1 - 1e-10),
+    delta ~ 1e-5.  Just above it rho(a, s) is 1 (a is affine in s); just below it is NaN.
+    A threshold slipped by a factor n (mean instead of sum on one side) moves the boundary
+    by sqrt(10) and fails one side."""
+    n = 10
+    s = np.array([1.0, -1.0] * (n // 2))
+    for delta, is_nan in ((1.01e-5, False), (0.99e-5, True), (3.2e-5, False), (3.1e-6, True)):
+        a = 1.0 + delta * s
+        for r in (O.pearson(a, s), O.pearson(s, a)):
+            if is_nan:
+                assert math.isnan(r), delta
+            else:
+                assert abs(r - 1.0) < 1e-9, (delta, r)
+    # a large offset with a healthy spread is not mistaken for a constant
+    a = 1e4 + 0.5 * s
+    assert abs(O.pearson(a, -s) + 1.0) < 1e-12
