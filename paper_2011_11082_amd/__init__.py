@@ -331,24 +331,77 @@ def ccm_matrix(ts: torch.Tensor, E_min: int = 1, E_max: int = E_MAX, tau: int = 
     return out, optE
 
 
+def storage_span_ok(t: torch.Tensor, first: int, last: int) -> bool:
+    """True when element offsets first .. last (counted from t's data pointer, in elements
+    of t's dtype) all lie inside t's storage.  A host-side check of the memory a kernel is
+    about to read or write through a raw pointer."""
+    if last < first:
+        return True   # an empty range
+    total = t.untyped_storage().nbytes() // t.element_size()
+    off = t.storage_offset()
+    return off + first >= 0 and off + last < total
+
+
 def crossmap_rho_backward(ts, lib_ts, nbr_idx, nbr_w, lib_E, pair_lib, pair_tgt, grad_rho,
                           tau: int = 1, grad_ts=None, grad_lib=None):
     """Adjoint of sum_p grad_rho[p] * rho[pair_lib[p], pair_tgt[p]] with fixed neighbour sets.
 
-    Accumulates into (and returns) grad_ts [L][ld] and grad_lib [n_lib][L] (float32)."""
+    ts is the [L][N] target panel (row stride ld >= N); pair_tgt are columns of it, in
+    [0, N), and pair_lib rows of the tables, in [0, n_lib).  Accumulates into (and returns)
+    grad_ts, an [L][N] view with ts's row stride (allocated as [L][ld] zeros when None), and
+    grad_lib [n_lib][L] (float32, zeros when None).  The kernels write grad_ts at
+    row * ld + column, so a caller's grad_ts must have ts's strides."""
     lib = load_library()
     ts, ld, L = _panel(ts)
+    N = int(ts.shape[1])
+    _dev(nbr_idx, "nbr_idx", torch.int32)
+    _dev(nbr_w, "nbr_w", torch.float32)
+    if nbr_idx.dim() != 3 or nbr_w.shape != nbr_idx.shape or int(nbr_idx.shape[1]) != L:
+        raise ValueError("tables must be [n_lib][L][k_max] with the panel's L")
+    if not (nbr_idx.is_contiguous() and nbr_w.is_contiguous()):
+        raise ValueError("tables must be contiguous")
     n_lib, _, k_max = nbr_idx.shape
     lib_E = _i32(lib_E, ts.device)
+    if lib_E.numel() != n_lib:
+        raise ValueError("lib_E needs one E per table")
     pair_lib = _i32(pair_lib, ts.device)
     pair_tgt = _i32(pair_tgt, ts.device)
     grad_rho = grad_rho.to(device=ts.device, dtype=torch.float32).contiguous()
     n_pairs = pair_lib.numel()
+    if pair_tgt.numel() != n_pairs or grad_rho.numel() != n_pairs:
+        raise ValueError("pair_lib, pair_tgt and grad_rho differ in length")
+    if n_pairs:
+        # the pair ids index the panel view and the tables: keep them inside both
+        lo_t, hi_t = int(pair_tgt.min()), int(pair_tgt.max())
+        lo_l, hi_l = int(pair_lib.min()), int(pair_lib.max())
+        if lo_t < 0 or hi_t >= N or lo_l < 0 or hi_l >= n_lib:
+            raise ValueError(f"pair ids out of range: targets in [{lo_t}, {hi_t}] for N = {N}, "
+                             f"libraries in [{lo_l}, {hi_l}] for n_lib = {n_lib}")
+    if not isinstance(lib_ts, torch.Tensor) or lib_ts.device != ts.device:
+        raise TypeError("lib_ts must be a tensor on the panel's device")
+    lib_ts = lib_ts.to(torch.float32).contiguous()
+    if tuple(lib_ts.shape) != (n_lib, L):
+        raise ValueError(f"lib_ts must be [n_lib][L] = [{n_lib}][{L}], got {tuple(lib_ts.shape)}")
     if grad_ts is None:
-        grad_ts = torch.zeros((L, ld), dtype=torch.float32, device=ts.device)
+        grad_ts = torch.zeros((L, ld), dtype=torch.float32, device=ts.device)[:, :N]
+    else:
+        _dev(grad_ts, "grad_ts", torch.float32)
+        if (grad_ts.device != ts.device or tuple(grad_ts.shape) != (L, N)
+                or grad_ts.stride() != (ld, 1)):
+            raise ValueError(f"grad_ts must be a float32 [L][N] = [{L}][{N}] tensor on the "
+                             f"panel's device with strides ({ld}, 1)")
     if grad_lib is None:
         grad_lib = torch.zeros((n_lib, L), dtype=torch.float32, device=ts.device)
-    lib_ts = lib_ts.to(torch.float32).contiguous()
+    else:
+        _dev(grad_lib, "grad_lib", torch.float32)
+        if (grad_lib.device != ts.device or tuple(grad_lib.shape) != (n_lib, L)
+                or not grad_lib.is_contiguous()):
+            raise ValueError(f"grad_lib must be a contiguous float32 [{n_lib}][{L}] tensor on "
+                             "the panel's device")
+    # every element the kernels touch: rows 0..L-1, columns 0..N-1 at stride ld
+    if not (storage_span_ok(ts, 0, (L - 1) * ld + N - 1)
+            and storage_span_ok(grad_ts, 0, (L - 1) * ld + N - 1)):
+        raise ValueError("panel or grad_ts storage is smaller than its [L][N] view")
     ws, need = _workspace(OP_CROSSMAP_BACKWARD, L, n_lib, n_pairs, k_max, ts.device)
     _check(lib.ccm_crossmap_rho_backward(_ptr(ts), ld, L, _ptr(lib_ts), _ptr(nbr_idx), _ptr(nbr_w),
                                          _ptr(lib_E), n_lib, k_max, tau, _ptr(pair_lib),
@@ -391,9 +444,10 @@ class CrossMapRho(torch.autograd.Function):
         pair_lib = nz[:, 0].to(torch.int32)
         pair_tgt = nz[:, 1].to(torch.int32)
         gvals = g[nz[:, 0], nz[:, 1]].contiguous()
-        gts = torch.zeros(Y.shape, dtype=torch.float32, device=Y.device)
-        glib = torch.zeros(X.shape, dtype=torch.float32, device=X.device)
-        crossmap_rho_backward(Y, X, idx, w, lib_E, pair_lib, pair_tgt, gvals, ctx.tau, gts, glib)
+        # Y may be a view of a wider panel (row stride > N): the target gradient is written at
+        # Y's strides, into an [L][ld] buffer whose [L][N] view is returned
+        gts, glib = crossmap_rho_backward(Y, X, idx, w, lib_E, pair_lib, pair_tgt, gvals,
+                                          ctx.tau)
         return glib, gts, None, None, None
 
 

@@ -414,14 +414,33 @@ __global__ __launch_bounds__(kWave) void bw_reduce_kernel(
 
 static size_t up256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Pairs are processed in chunks whose per-pair buffers fit in 2 GiB (and whose count fits in
+// grid.y of the scatter kernel).  Chunks run in pair order and each adds its pairs into the
+// gradients in pair order, so the result does not depend on the chunk size.
+static constexpr size_t kBwChunkBytes = (size_t)2 << 30;
+
+static size_t bw_pair_bytes(int L, int k_max) {
+  return 6 * (size_t)L * 4 + 2 * (size_t)L * k_max * 4 + 4;
+}
+
+extern "C" int ccm_backward_chunk_pairs(int L, int k_max) {
+  size_t c = kBwChunkBytes / bw_pair_bytes(L, k_max);
+  if (c < 1) c = 1;
+  if (c > 65535) c = 65535;
+  return (int)c;
+}
+
 extern "C" size_t ccm_backward_ws_bytes(int L, int n_lib, int n_pairs, int k_max) {
-  // yhat, H, Gy, tc, lc, the target columns: [P][L] floats; coefficients twice: [P][k_max][L] and [P][L k_max]
-  // floats; pair_ok: [P] ints; per library: CSR offsets [L + 1], entries, positions, weights
-  // and the m-major table copy, [L k_max] each
-  const size_t a = up256((size_t)n_pairs * L * 4);
-  const size_t c = up256((size_t)n_pairs * L * k_max * 4);
+  // per pair of a chunk: yhat, H, Gy, tc, lc, the target column ([P][L] floats each), the
+  // coefficients twice ([P][k_max][L] and [P][L k_max] floats) and pair_ok ([P] ints); per
+  // library: CSR offsets [L + 1], entries, positions, weights and the m-major table copy,
+  // [L k_max] each
+  const int chunk = ccm_backward_chunk_pairs(L, k_max);
+  const size_t P = (size_t)(n_pairs < chunk ? n_pairs : chunk);
+  const size_t a = up256(P * L * 4);
+  const size_t c = up256(P * L * k_max * 4);
   const size_t t = up256((size_t)n_lib * L * k_max * 4);
-  return 6 * a + 2 * c + up256((size_t)n_pairs * 4) + up256((size_t)n_lib * (L + 1) * 4) + 4 * t;
+  return 6 * a + 2 * c + up256(P * 4) + up256((size_t)n_lib * (L + 1) * 4) + 4 * t;
 }
 
 extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, const float* lib_ts,
@@ -431,21 +450,23 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
                                           float* grad_ts, float* grad_lib, void* ws,
                                           hipStream_t stream) {
   if (n_pairs == 0) return hipSuccess;
-  const size_t a = up256((size_t)n_pairs * L * 4);
+  const int chunk = ccm_backward_chunk_pairs(L, k_max);
+  const size_t P = (size_t)(n_pairs < chunk ? n_pairs : chunk);
+  const size_t a = up256(P * L * 4);
   char* base = (char*)ws;
   float* yhat = (float*)base;
   float* H = (float*)(base + a);
   float* Gy = (float*)(base + 2 * a);
   float* tc = (float*)(base + 3 * a);
   float* lc = (float*)(base + 4 * a);
-  const size_t c = up256((size_t)n_pairs * L * k_max * 4);
+  const size_t c = up256(P * L * k_max * 4);
   const size_t tb = up256((size_t)n_lib * L * k_max * 4);
   float* ycol = (float*)(base + 5 * a);
   float* com = (float*)(base + 6 * a);
   float* coT = (float*)(base + 6 * a + c);
   char* after_coef = base + 6 * a + 2 * c;
   int* pair_ok = (int*)after_coef;
-  int* csr_off = (int*)(after_coef + up256((size_t)n_pairs * 4));
+  int* csr_off = (int*)(after_coef + up256(P * 4));
   int* csr_ent = (int*)((char*)csr_off + up256((size_t)n_lib * (L + 1) * 4));
   int* csr_pos = (int*)((char*)csr_ent + tb);
   float* csr_w = (float*)((char*)csr_pos + tb);
@@ -459,22 +480,28 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
   static std::atomic<uint64_t> attr_pair{0};
   e = ccm::allow_lds_once((const void*)ccm::bw_pair_kernel, attr_pair);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(ccm::bw_pair_kernel, dim3(n_pairs), dim3(ccm::kBwThreads), (size_t)L * sizeof(float), stream, ts, ld, L,
-                     nbr_idx, nbr_w, lib_E, n_lib, k_max, tau, pair_lib, pair_tgt, grad_rho, yhat, H,
-                     Gy, pair_ok, ycol);
-  const int64_t rows = (int64_t)n_pairs * L;
-  hipLaunchKernelGGL(ccm::bw_coef_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, stream,
-                     ts, ld, L, lib_ts, nbr_idx, lib_E, k_max, tau, pair_lib, pair_tgt, n_pairs, H,
-                     pair_ok, csr_pos, ycol, com, coT);
   static std::atomic<uint64_t> attr_scatter{0};
   e = ccm::allow_lds_once((const void*)ccm::bw_scatter_kernel, attr_scatter);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(ccm::bw_scatter_kernel, dim3((L + 255) / 256, n_pairs), dim3(256),
-                     (size_t)2 * L * sizeof(float), stream, ts,
-                     ld, L, lib_ts, lib_E, k_max, tau, pair_lib, n_pairs, H, Gy, pair_ok, com, coT,
-                     csr_off, csr_ent, csr_w, idx_m, tc, lc);
-  hipLaunchKernelGGL(ccm::bw_reduce_kernel, dim3((L + ccm::kWave - 1) / ccm::kWave, ccm::kRedHash),
-                     dim3(ccm::kWave), 0, stream, ld, L, pair_lib, pair_tgt, n_pairs, pair_ok, tc, lc,
-                     grad_ts, grad_lib);
-  return hipGetLastError();
+  for (int p0 = 0; p0 < n_pairs; p0 += chunk) {
+    const int np = n_pairs - p0 < chunk ? n_pairs - p0 : chunk;
+    const int* pl = pair_lib + p0;
+    const int* pt = pair_tgt + p0;
+    hipLaunchKernelGGL(ccm::bw_pair_kernel, dim3(np), dim3(ccm::kBwThreads), (size_t)L * sizeof(float),
+                       stream, ts, ld, L, nbr_idx, nbr_w, lib_E, n_lib, k_max, tau, pl, pt,
+                       grad_rho + p0, yhat, H, Gy, pair_ok, ycol);
+    const int64_t rows = (int64_t)np * L;
+    hipLaunchKernelGGL(ccm::bw_coef_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, stream,
+                       ts, ld, L, lib_ts, nbr_idx, lib_E, k_max, tau, pl, pt, np, H, pair_ok, csr_pos,
+                       ycol, com, coT);
+    hipLaunchKernelGGL(ccm::bw_scatter_kernel, dim3((L + 255) / 256, np), dim3(256),
+                       (size_t)2 * L * sizeof(float), stream, ts, ld, L, lib_ts, lib_E, k_max, tau,
+                       pl, np, H, Gy, pair_ok, com, coT, csr_off, csr_ent, csr_w, idx_m, tc, lc);
+    hipLaunchKernelGGL(ccm::bw_reduce_kernel, dim3((L + ccm::kWave - 1) / ccm::kWave, ccm::kRedHash),
+                       dim3(ccm::kWave), 0, stream, ld, L, pl, pt, np, pair_ok, tc, lc, grad_ts,
+                       grad_lib);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }

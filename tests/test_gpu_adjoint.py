@@ -174,3 +174,45 @@ def test_adjoint_tau2_against_oracle(ccm):
     rl = _rel(gl.cpu().numpy().astype(np.float64), g_lib)
     print(f"adjoint tau=2 rel L2 error: targets {rt:.2e}, libraries {rl:.2e}")
     assert rt < 1e-3 and rl < 1e-3
+
+
+def test_adjoint_through_a_column_slice_of_a_wider_panel(ccm):
+    # Y is an [L][N] view of an [L][N + 16] panel (row stride > N, storage offset 5): the
+    # backward must write the target gradient at Y's strides, inside Y's columns only
+    import torch
+
+    w = synth.make("logistic64")
+    ts = w.panel
+    L, N = ts.shape
+    libs = np.array([3, 17, 40], dtype=np.int32)
+    lib_E = np.array([3, 2, 4], dtype=np.int32)
+    wide_np = np.full((L, N + 16), 7.0, dtype=np.float32)
+    wide_np[:, 5:5 + N] = ts
+    wide = torch.as_tensor(wide_np).cuda().requires_grad_(True)
+    Y = wide[:, 5:5 + N]
+    assert Y.stride(0) == N + 16 and not Y.is_contiguous()
+    X = torch.as_tensor(np.ascontiguousarray(ts[:, libs].T)).cuda().requires_grad_(True)
+    _say("adjoint through a strided target view")
+    rho = ccm.crossmap_rho_autograd(X, Y, lib_E)
+    rng = np.random.default_rng(52)
+    g = np.zeros((len(libs), N), dtype=np.float32)
+    pick = rng.choice(len(libs) * N, 10, replace=False)
+    g.flat[pick] = rng.standard_normal(10).astype(np.float32)
+    (rho * torch.as_tensor(g).cuda()).sum().backward()
+    gw = wide.grad.cpu().numpy().astype(np.float64)
+    assert not gw[:, :5].any() and not gw[:, 5 + N:].any()
+    idx_o, _, _ = O.knn(ts, libs, lib_E, 1, 0, int(lib_E.max()) + 1)
+    r_i, r_j = np.nonzero(g)
+    pairs = np.stack([r_i, r_j], axis=1).astype(np.int32)
+    g_tgt, g_lib = O.crossmap_rho_grad(ts, libs, lib_E, idx_o, 1, pairs, g[r_i, r_j])
+    rt = _rel(gw[:, 5:5 + N], g_tgt)
+    rl = _rel(X.grad.cpu().numpy().astype(np.float64), g_lib)
+    print(f"strided view: rel L2 error targets {rt:.2e}, libraries {rl:.2e}")
+    assert rt < 1e-3 and rl < 1e-3
+    # a caller's gradient buffer must carry the panel's strides
+    idx, wt, _ = ccm.knn(Y.detach(), libs, lib_E, k_max=5)
+    with pytest.raises(ValueError):
+        ccm.crossmap_rho_backward(Y.detach(), X.detach(), idx, wt, lib_E, [0], [1], torch.ones(1),
+                                  grad_ts=torch.zeros((L, N), device="cuda"))
+    with pytest.raises(ValueError):
+        ccm.crossmap_rho_backward(Y.detach(), X.detach(), idx, wt, lib_E, [0], [N], torch.ones(1))
