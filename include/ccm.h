@@ -159,6 +159,10 @@ ccm_status ccm_simplex_optE(const float* ts, int64_t ld, int32_t L, const int32_
  *     bytes plus 5.4 KB per 16 targets).
  *   precision CCM_PRECISION_BF16: target values and weights rounded to BF16, contracted on
  *   MFMA with FP32 accumulation; observed values FP32; FP64 moments.
+ *   Both forms first centre each target column on c_j, its mean over t = 0..L-1 rounded to
+ *   FP32, and work on y - c_j (rho is unchanged by a common shift of y and yhat, and the
+ *   weights of a row sum to 1), so a large offset of a series costs the FP32 and BF16
+ *   arithmetic no digits; the zero-variance test and the moments refer to the uncentred y.
  *   rho [n_lib][n_tgt]               output (row = library, column = target).
  *   moments [n_lib][n_tgt][3]        (nullable) FP64 sum(yhat), sum(yhat^2), sum(y*yhat).
  * Errors: EINVAL (nulls, sizes, precision), ERANGE (k_max, L), EWORKSPACE.
@@ -181,7 +185,8 @@ ccm_status ccm_crossmap_rho(const float* ts, int64_t ld, int32_t L, const int32_
  *   targets: series tgt0 .. tgt0 + n_tgt - 1 of ts.
  *   rho[i][j] = Pearson over t = (E_j-1) tau .. L-1 of (ts[t * ld + tgt0 + j], yhat_ij(t)),
  *   yhat_ij(t) = sum_k w[t,k] * ts[n_k(t) * ld + tgt0 + j] over library i's table at E_j;
- *   FP32 products and sums per prediction, FP64 moments; NaN where a variance vanishes.
+ *   FP32 products and sums per prediction (targets centred as in ccm_crossmap_rho), FP64
+ *   moments; NaN where a variance vanishes.
  *   rho [n_lib][n_tgt], moments [n_lib][n_tgt][3] (nullable) as in ccm_crossmap_rho.
  *   Targets are grouped by E on the device (no host synchronisation).
  *   Series longer than 2475 steps use the global tile copy as in ccm_crossmap_rho.

@@ -38,8 +38,8 @@ size_t ccm_bf16_lds_bytes();
 hipError_t ccm_launch_crossmap_bf16(const float* ts, int64_t ld, int L, int tau, int tgt0, int n_tgt,
                                     const int* nbr_idx, const float* nbr_w, const int* lib_E,
                                     int n_lib, int k_max, float* rho, double* moments, uint16_t* yt,
-                                    uint32_t* ent, int* stage_off, int* lib_k, int* order,
-                                    hipStream_t stream);
+                                    float* cref, uint32_t* ent, int* stage_off, int* lib_k,
+                                    int* order, hipStream_t stream);
 size_t ccm_backward_ws_bytes(int L, int n_lib, int n_pairs, int k_max);
 hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, const float* lib_ts,
                                const int* nbr_idx, const float* nbr_w, const int* lib_E, int n_lib,
@@ -116,10 +116,10 @@ TargetEWs target_E_ws(int L, int n_tab, int n_tgt, int k_max) {
   return w;
 }
 
-// Workspace of the BF16 cross-map: BF16 target panel (target-major), table entries sorted
-// by (stage, row quarter), their bucket offsets, lib_k, order.
+// Workspace of the BF16 cross-map: BF16 target panel (target-major), the targets' centring
+// values, table entries sorted by (stage, row quarter), their bucket offsets, lib_k, order.
 struct Bf16Ws {
-  size_t off_yt, off_ent, off_so, off_libk, off_order, total;
+  size_t off_yt, off_cref, off_ent, off_so, off_libk, off_order, total;
 };
 
 Bf16Ws bf16_ws(int L, int n_lib, int n_tgt) {
@@ -127,7 +127,8 @@ Bf16Ws bf16_ws(int L, int n_lib, int n_tgt) {
   const size_t nst = (size_t)(L + 63) / 64;
   const size_t nch = (size_t)(L + 127) / 128;
   w.off_yt = 0;
-  w.off_ent = align_up(w.off_yt + (size_t)n_tgt * nst * 64 * 2);
+  w.off_cref = align_up(w.off_yt + (size_t)n_tgt * nst * 64 * 2);
+  w.off_ent = align_up(w.off_cref + (size_t)n_tgt * 4);
   w.off_so = align_up(w.off_ent + (size_t)n_lib * nch * 128 * CCM_K_MAX * 4);
   w.off_libk = align_up(w.off_so + (size_t)n_lib * nch * (4 * nst + 1) * 4);
   w.off_order = align_up(w.off_libk + (size_t)n_lib * 4);
@@ -400,6 +401,7 @@ ccm_status ccm_crossmap_rho(const float* ts, int64_t ld, int32_t L, const int32_
     return device_status(
         fn, ccm_launch_crossmap_bf16(ts, ld, L, tau, tgt0, n_tgt, nbr_idx, nbr_w, lib_E, n_lib, k_max,
                                      rho, moments, (uint16_t*)(base + w.off_yt),
+                                     (float*)(base + w.off_cref),
                                      (uint32_t*)(base + w.off_ent), (int*)(base + w.off_so),
                                      (int*)(base + w.off_libk), (int*)(base + w.off_order),
                                      (hipStream_t)stream));

@@ -20,6 +20,10 @@
 //     table row so that at step j query t prefers a neighbour with s = t + j (mod 4),
 //     which keeps the four rows of a pass in distinct quarters whenever it can.
 //     The order of the k products only changes FP32 rounding.
+//   * Each target column is centred on its mean rounded to FP32 when the tile is loaded
+//     (rho does not change under a common shift of y and yhat, and the weights sum to 1, so
+//     yhat - c is the prediction of y - c); the FP32 products and moments then keep their
+//     digits whatever the series' offset.
 //   * Moments sum(yhat), sum(yhat^2), sum(y*yhat) are kept in FP32 for 32 blocks and folded
 //     into FP64; sum(y), sum(y^2) over each library's query range come from per-tile FP64
 //     column sums.  rho is formed in FP64.
@@ -385,10 +389,11 @@ __device__ __forceinline__ int tile_column(int T, int c, int n_tgt, const int* t
   return j < n_tgt ? j : -1;
 }
 
-// gtile[T][t][c] = Y(t, column c of tile T) (0 where no column), and the FP64 sums of y and
-// y^2 over t >= (E-1) tau for E = 1..20: gsum[T][0][E][c], gsum[T][1][E][c].  One workgroup
-// of 1024 threads per tile; a sum over t >= (E-1) tau is the column total less its first
-// (E-1) tau terms.
+// gtile[T][t][c] = Y(t, column c of tile T) - c_c (0 where no column), centred on the
+// column's mean rounded to FP32, c_c = gsum[T][0][0][c]; and the FP64 sums of those values
+// and their squares over t >= (E-1) tau for E = 1..20: gsum[T][0][E][c], gsum[T][1][E][c].
+// One workgroup of 1024 threads per tile; a sum over t >= (E-1) tau is the column total less
+// its first (E-1) tau terms.
 constexpr int kCopyThreads = 1024;
 
 template <int TJ>
@@ -398,6 +403,7 @@ __global__ __launch_bounds__(kCopyThreads) void tile_copy_kernel(
     float* __restrict__ gtile, double* __restrict__ gsum) {
   __shared__ double part[2][kCopyThreads];
   __shared__ int colmap[TJ];
+  __shared__ float cref[TJ];
   const int T = blockIdx.x;
   if (tiles && T >= *ntiles) return;
   if (threadIdx.x < TJ) colmap[threadIdx.x] = tile_column<TJ>(T, threadIdx.x, n_tgt, tiles, perm);
@@ -405,9 +411,22 @@ __global__ __launch_bounds__(kCopyThreads) void tile_copy_kernel(
   const int c = threadIdx.x & (TJ - 1);
   const int j = colmap[c];
   float* out = gtile + (size_t)T * L * TJ;
+  // centring value of each column: its mean rounded to FP32 (as for the LDS tile)
   double a = 0.0, a2 = 0.0;
+  for (int g = threadIdx.x; g < L * TJ; g += blockDim.x)
+    a += j >= 0 ? ts[(int64_t)(g / TJ) * ld + tgt0 + j] : 0.0f;
+  part[0][threadIdx.x] = a;
+  __syncthreads();
+  if (threadIdx.x < TJ) {
+    double tot = 0.0;
+    for (int r = c; r < kCopyThreads; r += TJ) tot += part[0][r];
+    cref[c] = (float)(tot / L);
+  }
+  __syncthreads();
+  const float cj = cref[c];
+  a = 0.0;
   for (int g = threadIdx.x; g < L * TJ; g += blockDim.x) {
-    const float v = j >= 0 ? ts[(int64_t)(g / TJ) * ld + tgt0 + j] : 0.0f;
+    const float v = j >= 0 ? ts[(int64_t)(g / TJ) * ld + tgt0 + j] - cj : 0.0f;
     out[g] = v;
     a += v;
     a2 += (double)v * v;
@@ -424,11 +443,12 @@ __global__ __launch_bounds__(kCopyThreads) void tile_copy_kernel(
     int t = 0;
     for (int E = 1; E <= kEMax; ++E) {
       for (; t < (E - 1) * tau && t < L; ++t) {
-        const double v = j >= 0 ? (double)ts[(int64_t)t * ld + tgt0 + j] : 0.0;
+        const double v = j >= 0 ? (double)(ts[(int64_t)t * ld + tgt0 + j] - cj) : 0.0;
         pre += q ? v * v : v;
       }
       o[E * TJ + c] = tot - pre;
     }
+    if (q == 0) o[c] = cj;   // the centring value, in the unused E = 0 slot
   }
 }
 
@@ -489,11 +509,31 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
     float* tile = (float*)smem;
     double* lsy = (double*)(smem + (size_t)L * kRowBytes);
     double* lsyy = lsy + (kEMax + 1) * kTJ;
-    // load the tile (rows 0..L-1, 16 columns; missing columns read as 0)
+    // load the tile (rows 0..L-1, 16 columns; missing columns read as 0).  A thread always
+    // handles the same column (blockDim is a multiple of 16), so it sums that column too.
+    double csum = 0.0;
     for (int g = threadIdx.x; g < L * kTJ; g += blockDim.x) {
       const int t = g >> 4;
       const int j = colmap[g & 15];
-      tile[g] = j >= 0 ? ts[(int64_t)t * ld + tgt0 + j] : 0.0f;
+      const float v = j >= 0 ? ts[(int64_t)t * ld + tgt0 + j] : 0.0f;
+      tile[g] = v;
+      csum += v;
+    }
+    // centre each column on c = its mean rounded to FP32 (kept in the unused E = 0 slot of
+    // the sums, lsy[c]); the per-wave partial sums pass through lsy[16 ..] first
+    csum += __shfl_xor(csum, 16);
+    csum += __shfl_xor(csum, 32);
+    if (lane_id() < kTJ) lsy[kTJ + (threadIdx.x / kWave) * kTJ + lane_id()] = csum;
+    __syncthreads();
+    if (threadIdx.x < kTJ) {
+      double tot = 0.0;
+      for (int w = 0; w < kGatherThreads / kWave; ++w) tot += lsy[kTJ + w * kTJ + threadIdx.x];
+      lsy[threadIdx.x] = (double)(float)(tot / L);
+    }
+    __syncthreads();
+    {
+      const float cj = (float)lsy[threadIdx.x & 15];
+      for (int g = threadIdx.x; g < L * kTJ; g += blockDim.x) tile[g] -= cj;
     }
     __syncthreads();
     // FP64 sums of y and y^2 over t >= (E-1) tau, per E and column
@@ -572,15 +612,13 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
         const int col = 4 * l + c;
         const int j = colmap[col];
         if (j >= 0) {
-          const double r = pearson_from_moments(n, sy[E * TJ + col], syy[E * TJ + col],
-                                                m.dp[c], m.dpp[c], m.dyp[c]);
+          const double cref = sy[col];   // the column's centring value (E = 0 slot)
+          const double r = pearson_shifted(n, cref, sy[E * TJ + col], syy[E * TJ + col],
+                                           m.dp[c], m.dpp[c], m.dyp[c]);
           rho[(size_t)i * n_tgt + j] = (float)r;
-          if (moments) {
-            double* mo = moments + ((size_t)i * n_tgt + j) * 3;
-            mo[0] = m.dp[c];
-            mo[1] = m.dpp[c];
-            mo[2] = m.dyp[c];
-          }
+          if (moments)
+            unshift_moments(n, cref, sy[E * TJ + col], m.dp[c], m.dpp[c], m.dyp[c],
+                            moments + ((size_t)i * n_tgt + j) * 3);
         }
       }
     }

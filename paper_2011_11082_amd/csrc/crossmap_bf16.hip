@@ -4,8 +4,9 @@
 // n x L matrix holding the simplex weights of row t at the columns of its k neighbours
 // (every other entry 0) and Y is the L x n_tgt target panel.  This form densifies W in
 // tiles and runs the product on the matrix cores: BF16 operands (weights and targets
-// rounded to nearest-even), FP32 accumulation, then the same Pearson epilogue as the FP32
-// gather with the observed targets in FP32 and the moments in FP64.  Distances and
+// rounded to nearest-even, each target column first centred on its mean rounded to FP32),
+// FP32 accumulation, then the same Pearson epilogue as the FP32 gather with the observed
+// targets in FP32 (centred the same way) and the moments in FP64.  Distances and
 // weights are computed in FP32/FP64 exactly as for the gather; only the product operands
 // are BF16.  The dense product does L / k times the multiply-adds of the gather, so this
 // form is bound by MFMA throughput.
@@ -59,18 +60,41 @@ __device__ __forceinline__ uint16_t bf16_bits(float f) {
   return __builtin_bit_cast(uint16_t, b);
 }
 
-// Y (time-major, FP32) -> Yt [n_tgt][Lpad] BF16, zero beyond L.
+// Centring value of each target column: its mean over t = 0..L-1 (FP64 sum) rounded to
+// FP32.  The BF16 operands and the FP32 epilogue sums work on y - c, so a large offset of a
+// series costs no digits (rho does not change under a common shift of y and yhat, and the
+// weights sum to 1).  Block = 64 columns x 4 row groups.
+__global__ __launch_bounds__(256) void column_ref_kernel(const float* __restrict__ ts, int64_t ld,
+                                                         int L, int tgt0, int n_tgt,
+                                                         float* __restrict__ cref) {
+  __shared__ double part[4][64];
+  const int tx = threadIdx.x & 63;
+  const int ty = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + tx;
+  double a = 0.0;
+  if (j < n_tgt)
+    for (int t = ty; t < L; t += 4) a += ts[(int64_t)t * ld + tgt0 + j];
+  part[ty][tx] = a;
+  __syncthreads();
+  if (ty == 0 && j < n_tgt)
+    cref[j] = (float)((part[0][tx] + part[1][tx] + part[2][tx] + part[3][tx]) / L);
+}
+
+// Y (time-major, FP32) -> Yt [n_tgt][Lpad] BF16 of y - c (c = cref of the column), zero
+// beyond L.
 __global__ __launch_bounds__(256) void transpose_bf16_kernel(const float* __restrict__ ts, int64_t ld,
                                                              int L, int tgt0, int n_tgt, int Lpad,
+                                                             const float* __restrict__ cref,
                                                              uint16_t* __restrict__ yt) {
   __shared__ float tile[64][65];
   const int j0 = blockIdx.x * 64;
   const int t0 = blockIdx.y * 64;
   const int tx = threadIdx.x & 63;
   const int ty = threadIdx.x >> 6;
+  const float cx = j0 + tx < n_tgt ? cref[j0 + tx] : 0.0f;
   for (int r = ty; r < 64; r += 4) {
     const int t = t0 + r, j = j0 + tx;
-    tile[r][tx] = (t < L && j < n_tgt) ? ts[(int64_t)t * ld + tgt0 + j] : 0.0f;
+    tile[r][tx] = (t < L && j < n_tgt) ? ts[(int64_t)t * ld + tgt0 + j] - cx : 0.0f;
   }
   __syncthreads();
   for (int r = ty; r < 64; r += 4) {
@@ -137,7 +161,7 @@ __global__ __launch_bounds__(kBRows) void bf16_entries_kernel(
 
 __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
     const float* __restrict__ ts, int64_t ld, int L, int tau, int tgt0, int n_tgt, int Lpad,
-    const uint16_t* __restrict__ yt, const uint32_t* __restrict__ ent,
+    const uint16_t* __restrict__ yt, const float* __restrict__ cref, const uint32_t* __restrict__ ent,
     const int* __restrict__ stage_off, const int* __restrict__ order, const int* __restrict__ lib_k,
     int n_lib, int nchunk_max, int nst, float* __restrict__ rho, double* __restrict__ moments) {
   extern __shared__ __align__(16) char smem[];
@@ -164,6 +188,13 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
   if (lane == 0) s_nchunk[wave] = nchunk;
   uint16_t* Aw = As + (size_t)wave * kHalf * kRS;
   for (int q = lane; q < kHalf * kRS / 2; q += kWave) ((uint32_t*)Aw)[q] = 0u;
+  // centring values of this lane's two columns (the epilogue works on y - c, as Yt does)
+  float cy[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int j = j0 + 32 * b + (lane & 31);
+    cy[b] = j < n_tgt ? cref[j] : 0.0f;
+  }
   // FP64 moment sums of this lane's two columns: y, y^2, yhat, yhat^2, y * yhat
   double M[5][2];
 #pragma unroll
@@ -278,7 +309,7 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
           if (full) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-              const float y = yb[(int64_t)(8 * (r >> 2) + (r & 3)) * ld];
+              const float y = yb[(int64_t)(8 * (r >> 2) + (r & 3)) * ld] - cy[b];
               const float p = acc[0][b][r];
               sy += y;
               syy = fmaf(y, y, syy);
@@ -290,7 +321,7 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
               if (trow + 8 * (r >> 2) + (r & 3) < L) {
-                const float y = yb[(int64_t)(8 * (r >> 2) + (r & 3)) * ld];
+                const float y = yb[(int64_t)(8 * (r >> 2) + (r & 3)) * ld] - cy[b];
                 const float p = acc[0][b][r];
                 sy += y;
                 syy = fmaf(y, y, syy);
@@ -335,14 +366,17 @@ __global__ __launch_bounds__(kBThreads, 2) void gather_bf16_kernel(
     }
     const int j = j0 + 32 * b + lane;
     if (j < n_tgt) {
-      const double r = k > 0 ? pearson_from_moments((double)nrows, S[0], S[1], S[2], S[3], S[4])
+      const double n = (double)nrows;
+      const double r = k > 0 ? pearson_shifted(n, cy[b], S[0], S[1], S[2], S[3], S[4])
                              : __builtin_nan("");
       rho[(size_t)i * n_tgt + j] = (float)r;
       if (moments) {
         double* mo = moments + ((size_t)i * n_tgt + j) * 3;
-        mo[0] = k > 0 ? S[2] : __builtin_nan("");
-        mo[1] = k > 0 ? S[3] : __builtin_nan("");
-        mo[2] = k > 0 ? S[4] : __builtin_nan("");
+        if (k > 0) {
+          unshift_moments(n, cy[b], S[0], S[2], S[3], S[4], mo);
+        } else {
+          mo[0] = mo[1] = mo[2] = __builtin_nan("");
+        }
       }
     }
   }
@@ -360,15 +394,17 @@ extern "C" size_t ccm_bf16_lds_bytes() {
 extern "C" hipError_t ccm_launch_crossmap_bf16(const float* ts, int64_t ld, int L, int tau, int tgt0,
                                                int n_tgt, const int* nbr_idx, const float* nbr_w,
                                                const int* lib_E, int n_lib, int k_max, float* rho,
-                                               double* moments, uint16_t* yt, uint32_t* ent,
-                                               int* stage_off, int* lib_k, int* order,
-                                               hipStream_t stream) {
+                                               double* moments, uint16_t* yt, float* cref,
+                                               uint32_t* ent, int* stage_off, int* lib_k,
+                                               int* order, hipStream_t stream) {
   if (n_lib == 0 || n_tgt == 0) return hipSuccess;
   const int nst = (L + ccm::kStage - 1) / ccm::kStage;
   const int Lpad = nst * ccm::kStage;
   const int nchunk_max = (L + ccm::kBRows - 1) / ccm::kBRows;
+  hipLaunchKernelGGL(ccm::column_ref_kernel, dim3((n_tgt + 63) / 64), dim3(256), 0, stream, ts, ld,
+                     L, tgt0, n_tgt, cref);
   hipLaunchKernelGGL(ccm::transpose_bf16_kernel, dim3((n_tgt + 63) / 64, Lpad / 64), dim3(256), 0,
-                     stream, ts, ld, L, tgt0, n_tgt, Lpad, yt);
+                     stream, ts, ld, L, tgt0, n_tgt, Lpad, (const float*)cref, yt);
   hipLaunchKernelGGL(ccm::bf16_entries_kernel, dim3(nchunk_max, n_lib), dim3(ccm::kBRows), 0, stream,
                      nbr_idx, nbr_w, lib_E, L, k_max, tau, nchunk_max, nst, ent, stage_off, lib_k);
   hipError_t e = ccm_launch_order(lib_k, n_lib, order, stream);
@@ -378,6 +414,7 @@ extern "C" hipError_t ccm_launch_crossmap_bf16(const float* ts, int64_t ld, int 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(ccm::gather_bf16_kernel, dim3((n_lib + 1) / 2, (n_tgt + ccm::kBTN - 1) / ccm::kBTN),
                      dim3(ccm::kBThreads), ccm_bf16_lds_bytes(), stream, ts, ld, L, tau, tgt0, n_tgt,
-                     Lpad, yt, ent, stage_off, order, lib_k, n_lib, nchunk_max, nst, rho, moments);
+                     Lpad, yt, (const float*)cref, ent, stage_off, order, lib_k, n_lib, nchunk_max,
+                     nst, rho, moments);
   return hipGetLastError();
 }

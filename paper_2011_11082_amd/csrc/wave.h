@@ -108,4 +108,27 @@ __device__ __forceinline__ double pearson_from_moments(double n, double sy, doub
   return (n * syp - sy * sp) / sqrt(vy * vp);
 }
 
+// The same from moments of shifted values y' = y - c and p' = p - c, where c is a reference
+// value of the target column (its mean rounded to FP32): Pearson's rho does not change under
+// a common shift, and with the column centred the FP32 products and one-pass moments no
+// longer lose digits to a large mean.  The zero-variance test still compares with the raw
+// second moments, sum (y' + c)^2 = syy' + c (2 sy' + n c), as for unshifted moments.
+__device__ __forceinline__ double pearson_shifted(double n, double c, double sy, double syy,
+                                                  double sp, double spp, double syp) {
+  const double vy = n * syy - sy * sy;
+  const double vp = n * spp - sp * sp;
+  const double ryy = syy + c * (2.0 * sy + n * c);
+  const double rpp = spp + c * (2.0 * sp + n * c);
+  if (!(vy > 1e-10 * n * ryy) || !(vp > 1e-10 * n * rpp)) return __builtin_nan("");
+  return (n * syp - sy * sp) / sqrt(vy * vp);
+}
+
+// Raw moments sum(p), sum(p^2), sum(y p) from shifted ones (p = p' + c, y = y' + c).
+__device__ __forceinline__ void unshift_moments(double n, double c, double sy, double sp,
+                                                double spp, double syp, double* out) {
+  out[0] = sp + n * c;
+  out[1] = spp + c * (2.0 * sp + n * c);
+  out[2] = syp + c * (sy + sp + n * c);
+}
+
 }  // namespace ccm
