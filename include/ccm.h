@@ -15,7 +15,8 @@
  *   - Every function returns a ccm_status.  No C++ exception crosses this boundary.
  *   - Array arguments are DEVICE pointers owned by the caller, unless stated otherwise.
  *     The library keeps no allocation between calls; scratch space is the caller's
- *     workspace (size from ccm_workspace_size).
+ *     workspace (size from ccm_workspace_size).  The one exception is the static device
+ *     array behind ccm_simplex_optE_noalloc.
  *   - Every call is asynchronous on `stream` (a hipStream_t passed as void*, NULL = the
  *     default stream) and never synchronises the host.  Device-side problems that cannot
  *     be seen without a synchronisation (a library E out of range) are reported in the
@@ -144,6 +145,27 @@ ccm_status ccm_simplex_optE(const float* ts, int64_t ld, int32_t L, const int32_
                             int32_t n, int32_t E_min, int32_t E_max, int32_t tau, int32_t Tp,
                             int32_t mode, int32_t* optE, float* rho_E, void* ws,
                             size_t ws_bytes, void* stream);
+
+/*
+ * ccm_simplex_optE_noalloc -- ccm_simplex_optE for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, outputs, kernels and results as ccm_simplex_optE, without the
+ * workspace: the per-(series, E) FP64 skills live in a static device array of the library
+ * (16 MiB, CCM_NOALLOC_MAX_SERIES x CCM_E_MAX doubles), one per GPU, held from the first
+ * call on that GPU until the process ends.  The call makes no hipMalloc, hipFree or other
+ * allocating call; its first call on a device looks up the array's device address once.
+ *   n                 at most CCM_NOALLOC_MAX_SERIES (ERANGE beyond it).
+ * Calls on one GPU share its array: calls that overlap in time on that GPU (on different
+ * streams, or from different host threads without ordering) race and give undefined
+ * outputs; calls ordered on one stream are safe.  The debug finiteness check
+ * (ccm_set_check_finite) is not applied here (it allocates).
+ * Errors: as ccm_simplex_optE, plus ERANGE for n > CCM_NOALLOC_MAX_SERIES.
+ */
+#define CCM_NOALLOC_MAX_SERIES 104857
+ccm_status ccm_simplex_optE_noalloc(const float* ts, int64_t ld, int32_t L, const int32_t* ids,
+                                    int32_t n, int32_t E_min, int32_t E_max, int32_t tau,
+                                    int32_t Tp, int32_t mode, int32_t* optE, float* rho_E,
+                                    void* stream);
 
 /*
  * ccm_crossmap_rho -- cross-map every target with every library table and reduce each

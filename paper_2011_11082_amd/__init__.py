@@ -29,7 +29,8 @@ PRECISION_FP32, PRECISION_BF16 = 0, 1
  OP_CROSSMAP_TARGET_E) = range(7)
 
 EXPORTED = (
-    "ccm_embed", "ccm_knn", "ccm_knn_subset", "ccm_simplex_optE", "ccm_crossmap_rho",
+    "ccm_embed", "ccm_knn", "ccm_knn_subset", "ccm_simplex_optE", "ccm_simplex_optE_noalloc",
+    "ccm_crossmap_rho",
     "ccm_crossmap_rho_backward", "ccm_crossmap_rho_target_E", "ccm_workspace_size",
     "ccm_set_check_finite", "ccm_status_string", "ccm_last_error", "ccm_version",
 )
@@ -66,6 +67,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
                            _SZ, _P],
         "ccm_simplex_optE": [_P, _I64, _I32, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P,
                              _SZ, _P],
+        "ccm_simplex_optE_noalloc": [_P, _I64, _I32, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P,
+                                     _P, _P],
         "ccm_crossmap_rho": [_P, _I64, _I32, _P, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _P,
                              _P, _P, _SZ, _P],
         "ccm_crossmap_rho_backward": [_P, _I64, _I32, _P, _P, _P, _P, _I32, _I32, _I32, _P, _P,
@@ -203,6 +206,29 @@ def simplex_optE(ts: torch.Tensor, ids, E_min: int = 1, E_max: int = E_MAX, tau:
     _check(lib.ccm_simplex_optE(_ptr(ts), ld, L, _ptr(ids), n, E_min, E_max, tau, Tp, mode,
                                 _ptr(optE), _ptr(rho_E), _ptr(ws), need, _stream()))
     return optE, rho_E
+
+
+NOALLOC_MAX_SERIES = 104857
+
+
+def simplex_optE_noalloc(ts: torch.Tensor, ids, optE: torch.Tensor, rho_E: torch.Tensor,
+                         E_min: int = 1, E_max: int = E_MAX, tau: int = 1, Tp: int = 1,
+                         mode: int = MODE_LOO) -> None:
+    """ccm_simplex_optE_noalloc into the caller's optE (int32 [n]) and rho_E (float32
+    [n][E_max-E_min+1]) on ts's device: no workspace, nothing allocated by the call.  ids
+    must already be an int32 device tensor."""
+    lib = load_library()
+    ts, ld, L = _panel(ts)
+    for t, name, dt in ((ids, "ids", torch.int32), (optE, "optE", torch.int32),
+                        (rho_E, "rho_E", torch.float32)):
+        _dev(t, name, dt)
+        if t.device != ts.device or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous on the panel's device")
+    n = ids.numel()
+    if optE.numel() != n or tuple(rho_E.shape) != (n, E_max - E_min + 1):
+        raise ValueError("optE must be [n] and rho_E [n][E_max-E_min+1]")
+    _check(lib.ccm_simplex_optE_noalloc(_ptr(ts), ld, L, _ptr(ids), n, E_min, E_max, tau, Tp,
+                                        mode, _ptr(optE), _ptr(rho_E), _stream()))
 
 
 def crossmap_rho(ts: torch.Tensor, nbr_idx: torch.Tensor, nbr_w: torch.Tensor, lib_E,

@@ -41,6 +41,8 @@ hipError_t ccm_launch_crossmap_bf16(const float* ts, int64_t ld, int L, int tau,
                                     float* cref, uint32_t* ent, int* stage_off, int* lib_k,
                                     int* order, hipStream_t stream);
 size_t ccm_backward_ws_bytes(int L, int n_lib, int n_pairs, int k_max);
+int ccm_noalloc_max_series();
+hipError_t ccm_noalloc_scratch(double** out);
 hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, const float* lib_ts,
                                const int* nbr_idx, const float* nbr_w, const int* lib_E, int n_lib,
                                int k_max, int tau, const int* pair_lib, const int* pair_tgt,
@@ -330,18 +332,25 @@ ccm_status ccm_knn_subset(const float* ts, int64_t ld, int32_t L, const int32_t*
                     nbr_idx, nbr_w, nbr_d2, stream);
 }
 
-ccm_status ccm_simplex_optE(const float* ts, int64_t ld, int32_t L, const int32_t* ids, int32_t n,
-                            int32_t E_min, int32_t E_max, int32_t tau, int32_t Tp, int32_t mode,
-                            int32_t* optE, float* rho_E, void* ws, size_t ws_bytes, void* stream) {
-  const char* fn = "ccm_simplex_optE";
-  ccm_status st = CCM_OK;
-  if (!check_series(fn, &st, ts, ld, L, tau)) return st;
-  if (n < 0) return fail(CCM_EINVAL, fn, "n < 0");
-  if (n > 0 && (!ids || !optE)) return fail(CCM_EINVAL, fn, "ids or optE is NULL");
-  if (mode != CCM_MODE_LOO && mode != CCM_MODE_HALF) return fail(CCM_EINVAL, fn, "unknown mode");
-  if (Tp < 0) return fail(CCM_EINVAL, fn, "Tp < 0");
-  if (E_min < 1 || E_max > CCM_E_MAX || E_min > E_max)
-    return fail(CCM_ERANGE, fn, "need 1 <= E_min <= E_max <= CCM_E_MAX");
+}  // extern "C"
+
+namespace {
+// Argument checks shared by both optE entry points.
+bool check_simplex(const char* fn, ccm_status* st, const float* ts, int64_t ld, int32_t L,
+                   const int32_t* ids, int32_t n, int32_t E_min, int32_t E_max, int32_t tau,
+                   int32_t Tp, int32_t mode, const int32_t* optE) {
+  if (!check_series(fn, st, ts, ld, L, tau)) return false;
+  if (n < 0) { *st = fail(CCM_EINVAL, fn, "n < 0"); return false; }
+  if (n > 0 && (!ids || !optE)) { *st = fail(CCM_EINVAL, fn, "ids or optE is NULL"); return false; }
+  if (mode != CCM_MODE_LOO && mode != CCM_MODE_HALF) {
+    *st = fail(CCM_EINVAL, fn, "unknown mode");
+    return false;
+  }
+  if (Tp < 0) { *st = fail(CCM_EINVAL, fn, "Tp < 0"); return false; }
+  if (E_min < 1 || E_max > CCM_E_MAX || E_min > E_max) {
+    *st = fail(CCM_ERANGE, fn, "need 1 <= E_min <= E_max <= CCM_E_MAX");
+    return false;
+  }
   // admissible candidates at the largest E must cover k = E_max + 1
   const int64_t lo = (int64_t)(E_max - 1) * tau;
   int64_t ncand;
@@ -349,7 +358,22 @@ ccm_status ccm_simplex_optE(const float* ts, int64_t ld, int32_t L, const int32_
     ncand = (L - 1 - Tp) - lo + 1 - 1;  // query excluded
   else
     ncand = (L / 2 - 1 - Tp) - lo + 1;
-  if (ncand < E_max + 1) return fail(CCM_ERANGE, fn, "too few points for k = E_max + 1 neighbours");
+  if (ncand < E_max + 1) {
+    *st = fail(CCM_ERANGE, fn, "too few points for k = E_max + 1 neighbours");
+    return false;
+  }
+  return true;
+}
+}  // namespace
+
+extern "C" {
+
+ccm_status ccm_simplex_optE(const float* ts, int64_t ld, int32_t L, const int32_t* ids, int32_t n,
+                            int32_t E_min, int32_t E_max, int32_t tau, int32_t Tp, int32_t mode,
+                            int32_t* optE, float* rho_E, void* ws, size_t ws_bytes, void* stream) {
+  const char* fn = "ccm_simplex_optE";
+  ccm_status st = CCM_OK;
+  if (!check_simplex(fn, &st, ts, ld, L, ids, n, E_min, E_max, tau, Tp, mode, optE)) return st;
   if (n == 0) return CCM_OK;
   const size_t need = align_up((size_t)n * CCM_E_MAX * sizeof(double));
   if (!ws || ws_bytes < need) return fail(CCM_EWORKSPACE, fn, "workspace too small");
@@ -358,6 +382,25 @@ ccm_status ccm_simplex_optE(const float* ts, int64_t ld, int32_t L, const int32_
   if ((st = check_finite(fn, f, (hipStream_t)stream)) != CCM_OK) return st;
   return device_status(fn, ccm_launch_simplex(ts, ld, L, ids, n, E_min, E_max, tau, Tp, mode, optE,
                                               rho_E, (double*)ws, (hipStream_t)stream));
+}
+
+ccm_status ccm_simplex_optE_noalloc(const float* ts, int64_t ld, int32_t L, const int32_t* ids,
+                                    int32_t n, int32_t E_min, int32_t E_max, int32_t tau,
+                                    int32_t Tp, int32_t mode, int32_t* optE, float* rho_E,
+                                    void* stream) {
+  const char* fn = "ccm_simplex_optE_noalloc";
+  ccm_status st = CCM_OK;
+  if (!check_simplex(fn, &st, ts, ld, L, ids, n, E_min, E_max, tau, Tp, mode, optE)) return st;
+  if (n > ccm_noalloc_max_series())
+    return fail(CCM_ERANGE, fn, "n exceeds CCM_NOALLOC_MAX_SERIES (the static scratch)");
+  if (n == 0) return CCM_OK;
+  // every skill the finalize step reads is written earlier in the same call, so the shared
+  // scratch needs no clearing
+  double* scratch = nullptr;
+  hipError_t e = ccm_noalloc_scratch(&scratch);
+  if (e != hipSuccess) return device_status(fn, e);
+  return device_status(fn, ccm_launch_simplex(ts, ld, L, ids, n, E_min, E_max, tau, Tp, mode, optE,
+                                              rho_E, scratch, (hipStream_t)stream));
 }
 
 ccm_status ccm_crossmap_rho(const float* ts, int64_t ld, int32_t L, const int32_t* nbr_idx,

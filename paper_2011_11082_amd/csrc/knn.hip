@@ -636,6 +636,41 @@ extern "C" hipError_t ccm_launch_simplex(const float* ts, int64_t ld, int L, con
   return hipGetLastError();
 }
 
+// ---- static scratch of the allocation-free optE entry point ----------------------------
+// The FP64 skills [series][CCM_E_MAX] of up to kNoAllocSeries series (16 MiB), a file-scope
+// device array: each GPU the library runs on holds its own copy until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it is only a stand-in for the
+// symbol); it uses the device address that hipGetSymbolAddress returns for the current
+// device, looked up once per device and kept.
+namespace ccm {
+constexpr int kNoAllocSeries = 104857;   // floor(2^21 / 20): 2^21 doubles
+constexpr int kMaxDevices = 64;
+}  // namespace ccm
+
+static __device__ __align__(256) double scratch[(size_t)ccm::kNoAllocSeries * ccm::kEMax];
+
+extern "C" int ccm_noalloc_max_series() { return ccm::kNoAllocSeries; }
+
+// Device address of the current device's scratch (looked up on the first call per device).
+extern "C" hipError_t ccm_noalloc_scratch(double** out) {
+  static std::atomic<double*> ptrs[ccm::kMaxDevices];
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= ccm::kMaxDevices) return hipErrorInvalidDevice;
+  double* p = ptrs[dev].load(std::memory_order_acquire);
+  if (!p) {
+    void* addr = nullptr;
+    e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!addr) return hipErrorInvalidSymbol;
+    p = (double*)addr;
+    ptrs[dev].store(p, std::memory_order_release);   // same value if two threads race here
+  }
+  *out = p;
+  return hipSuccess;
+}
+
 extern "C" hipError_t ccm_launch_embed(const float* ts, int64_t ld, int L, const int* ids, int n,
                                        int E, int tau, float* emb, hipStream_t stream) {
   int64_t total = (int64_t)n * (L - (E - 1) * tau) * E;

@@ -52,6 +52,15 @@ int main() {
                                          NULL), CCM_ERANGE);
   expect("optE ws", ccm_simplex_optE(fp, 4, 100, ip, 1, 1, 5, 1, 1, 0, ip, fp, dp, 8, NULL),
          CCM_EWORKSPACE);
+  expect("optE noalloc size", ccm_simplex_optE_noalloc(fp, 4, 100, ip, CCM_NOALLOC_MAX_SERIES + 1,
+                                                       1, 5, 1, 1, 0, ip, fp, NULL),
+         CCM_ERANGE);
+  expect("optE noalloc mode", ccm_simplex_optE_noalloc(fp, 4, 100, ip, 1, 1, 5, 1, 1, 7, ip, fp,
+                                                       NULL),
+         CCM_EINVAL);
+  expect("optE noalloc empty", ccm_simplex_optE_noalloc(fp, 4, 100, ip, 0, 1, 5, 1, 1, 0, ip, fp,
+                                                        NULL),
+         CCM_OK);
 
   expect("crossmap precision", ccm_crossmap_rho(fp, 4, 100, ip, fp, ip, 1, 4, 1, 0, 4, 9, fp,
                                                 NULL, dp, 1 << 20, NULL), CCM_EINVAL);

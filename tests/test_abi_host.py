@@ -202,3 +202,24 @@ def test_storage_span_check():
     assert not ccm.storage_span_ok(tight, 0, (L - 1) * ld + N - 1)
     assert ccm.storage_span_ok(torch.zeros((L, ld))[:, :N], 0, (L - 1) * ld + N - 1)
     assert ccm.storage_span_ok(tight, 5, 4)                      # empty range
+
+
+def test_noalloc_optE_argument_errors_before_device_work():
+    # the allocation-free optE checks its arguments and its size limit on the host, before
+    # it looks up its static scratch or launches anything
+    lib = ccm.load_library()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced
+    assert lib.ccm_simplex_optE_noalloc(fake, 8, 100, fake, ccm.NOALLOC_MAX_SERIES + 1, 1, 10,
+                                        1, 1, 0, fake, _null(), _null()) == ccm.CCM_ERANGE
+    assert b"CCM_NOALLOC_MAX_SERIES" in lib.ccm_last_error()
+    assert lib.ccm_simplex_optE_noalloc(fake, 8, 100, fake, 1, 0, 5, 1, 1, 0, fake, _null(),
+                                        _null()) == ccm.CCM_ERANGE
+    assert lib.ccm_simplex_optE_noalloc(_null(), 8, 100, fake, 1, 1, 5, 1, 1, 0, fake, _null(),
+                                        _null()) == ccm.CCM_EINVAL
+    assert lib.ccm_simplex_optE_noalloc(fake, 8, 100, fake, 1, 1, 5, 1, 1, 7, fake, _null(),
+                                        _null()) == ccm.CCM_EINVAL
+    assert lib.ccm_simplex_optE_noalloc(fake, 8, 100, fake, 0, 1, 5, 1, 1, 0, fake, _null(),
+                                        _null()) == ccm.CCM_OK
+    # the limit in the header and in the binding agree with the library's
+    text = open(HEADER).read()
+    assert f"#define CCM_NOALLOC_MAX_SERIES {ccm.NOALLOC_MAX_SERIES}" in text
