@@ -57,10 +57,11 @@ __global__ __launch_bounds__(kBwThreads) void bw_pair_kernel(
     const float* __restrict__ nbr_w, const int* __restrict__ lib_E, int n_lib, int k_max, int tau,
     const int* __restrict__ pair_lib, const int* __restrict__ pair_tgt,
     const float* __restrict__ grad_rho, float* __restrict__ yhat, float* __restrict__ H,
-    float* __restrict__ Gy, int* __restrict__ pair_ok, float* __restrict__ ycol) {
+    float* __restrict__ Gy, int* __restrict__ pair_ok, float* __restrict__ ycol,
+    const int* __restrict__ perm) {
   __shared__ double red[kBwThreads / kWave];
   extern __shared__ float yl[];   // the pair's target column, [L]
-  const int p = blockIdx.x;
+  const int p = perm ? perm[blockIdx.x] : blockIdx.x;
   const int i = pair_lib[p];
   const int j = pair_tgt[p];
   const int E = (i >= 0 && i < n_lib) ? lib_E[i] : 0;
@@ -198,10 +199,11 @@ __global__ __launch_bounds__(256) void bw_coef_kernel(
     const int* __restrict__ nbr_idx, const int* __restrict__ lib_E, int k_max, int tau,
     const int* __restrict__ pair_lib, const int* __restrict__ pair_tgt, int n_pairs,
     const float* __restrict__ H, const int* __restrict__ pair_ok, const int* __restrict__ csr_pos,
-    const float* __restrict__ ycol, float* __restrict__ com, float* __restrict__ coT) {
+    const float* __restrict__ ycol, float* __restrict__ com, float* __restrict__ coT,
+    const int* __restrict__ perm) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= (int64_t)n_pairs * L) return;
-  const int p = (int)(g / L);
+  const int p = perm ? perm[(int)(g / L)] : (int)(g / L);
   const int t = (int)(g % L);
   float* cm_out = com + (size_t)p * k_max * L + t;     // stride L between m
   const int i = pair_lib[p];
@@ -311,9 +313,10 @@ __global__ __launch_bounds__(256) void bw_scatter_kernel(
     int n_pairs, const float* __restrict__ H, const float* __restrict__ Gy,
     const int* __restrict__ pair_ok, const float* __restrict__ com, const float* __restrict__ coT,
     const int* __restrict__ csr_off, const int* __restrict__ csr_ent, const float* __restrict__ csr_w,
-    const int* __restrict__ idx_m, float* __restrict__ tc, float* __restrict__ lc) {
+    const int* __restrict__ idx_m, float* __restrict__ tc, float* __restrict__ lc,
+    const int* __restrict__ perm) {
   extern __shared__ float sm[];   // the library series [L], then the pair's H [L]
-  const int p = blockIdx.y;
+  const int p = perm ? perm[blockIdx.y] : blockIdx.y;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   float* tco = tc + (size_t)p * L;
   float* lco = lc + (size_t)p * L;
@@ -372,6 +375,53 @@ __global__ __launch_bounds__(256) void bw_scatter_kernel(
   lco[s] = (float)Lb;
 }
 
+// Pairs of a chunk grouped by library (a counting sort in LDS, for up to kOrderMaxLib
+// libraries): the per-pair kernels take pair perm[b] at position b, so pairs of one library
+// run together and share its table, lists and series in L2.  Only the processing order
+// changes: every pair writes its own buffers, and the contributions are added in pair order
+// afterwards.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderMaxLib = 16384;
+
+__global__ __launch_bounds__(kOrderThreads) void bw_pair_order_kernel(
+    const int* __restrict__ pair_lib, int np, int n_lib, int* __restrict__ perm) {
+  extern __shared__ int cnt[];   // [n_lib + 1] (bucket n_lib: library ids out of range)
+  int* csum = cnt + n_lib + 1;   // [kOrderThreads]
+  const int nb = n_lib + 1;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) cnt[b] = 0;
+  __syncthreads();
+  for (int p = threadIdx.x; p < np; p += blockDim.x) {
+    const int i = pair_lib[p];
+    atomicAdd(&cnt[(i >= 0 && i < n_lib) ? i : n_lib], 1);
+  }
+  __syncthreads();
+  const int chunk = (nb + kOrderThreads - 1) / kOrderThreads;
+  const int c0 = min((int)threadIdx.x * chunk, nb), c1 = min(c0 + chunk, nb);
+  int acc = 0;
+  for (int q = c0; q < c1; ++q) {
+    const int c = cnt[q];
+    cnt[q] = acc;
+    acc += c;
+  }
+  csum[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int th = 0; th < kOrderThreads; ++th) {
+      const int c = csum[th];
+      csum[th] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int q = c0; q < c1; ++q) cnt[q] += csum[threadIdx.x];
+  __syncthreads();
+  for (int p = threadIdx.x; p < np; p += blockDim.x) {
+    const int i = pair_lib[p];
+    perm[atomicAdd(&cnt[(i >= 0 && i < n_lib) ? i : n_lib], 1)] = p;
+  }
+}
+
 // grad_ts[s][tgt_p] += tc[p][s], grad_lib[lib_p][s] += lc[p][s], pairs in order.  One wave
 // per (64 consecutive s, hash h): it takes the pairs whose target (for grad_ts) or library
 // (for grad_lib) is congruent to h modulo kRedHash, in pair order, so every output element
@@ -420,7 +470,7 @@ static size_t up256(size_t v) { return (v + 255) & ~(size_t)255; }
 static constexpr size_t kBwChunkBytes = (size_t)2 << 30;
 
 static size_t bw_pair_bytes(int L, int k_max) {
-  return 6 * (size_t)L * 4 + 2 * (size_t)L * k_max * 4 + 4;
+  return 6 * (size_t)L * 4 + 2 * (size_t)L * k_max * 4 + 8;
 }
 
 extern "C" int ccm_backward_chunk_pairs(int L, int k_max) {
@@ -432,15 +482,16 @@ extern "C" int ccm_backward_chunk_pairs(int L, int k_max) {
 
 extern "C" size_t ccm_backward_ws_bytes(int L, int n_lib, int n_pairs, int k_max) {
   // per pair of a chunk: yhat, H, Gy, tc, lc, the target column ([P][L] floats each), the
-  // coefficients twice ([P][k_max][L] and [P][L k_max] floats) and pair_ok ([P] ints); per
-  // library: CSR offsets [L + 1], entries, positions, weights and the m-major table copy,
-  // [L k_max] each
+  // coefficients twice ([P][k_max][L] and [P][L k_max] floats), pair_ok and the processing
+  // order ([P] ints each); per library: CSR offsets [L + 1], entries, positions, weights and
+  // the m-major table copy, [L k_max] each
   const int chunk = ccm_backward_chunk_pairs(L, k_max);
   const size_t P = (size_t)(n_pairs < chunk ? n_pairs : chunk);
   const size_t a = up256(P * L * 4);
   const size_t c = up256(P * L * k_max * 4);
   const size_t t = up256((size_t)n_lib * L * k_max * 4);
-  return 6 * a + 2 * c + up256(P * 4) + up256((size_t)n_lib * (L + 1) * 4) + 4 * t;
+  return 6 * a + 2 * c + up256(P * 4) + up256((size_t)n_lib * (L + 1) * 4) + 4 * t +
+         up256(P * 4);   // the pairs' processing order
 }
 
 extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, const float* lib_ts,
@@ -471,6 +522,7 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
   int* csr_pos = (int*)((char*)csr_ent + tb);
   float* csr_w = (float*)((char*)csr_pos + tb);
   int* idx_m = (int*)((char*)csr_w + tb);
+  int* perm = (int*)((char*)idx_m + tb);
   static std::atomic<uint64_t> attr{0};
   hipError_t e = ccm::allow_lds_once((const void*)ccm::bw_transpose_kernel, attr);
   if (e != hipSuccess) return e;
@@ -483,20 +535,30 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
   static std::atomic<uint64_t> attr_scatter{0};
   e = ccm::allow_lds_once((const void*)ccm::bw_scatter_kernel, attr_scatter);
   if (e != hipSuccess) return e;
+  static std::atomic<uint64_t> attr_order{0};
+  e = ccm::allow_lds_once((const void*)ccm::bw_pair_order_kernel, attr_order);
+  if (e != hipSuccess) return e;
+  const bool sorted = n_lib <= ccm::kOrderMaxLib;
+  const int* pord = sorted ? (const int*)perm : nullptr;
   for (int p0 = 0; p0 < n_pairs; p0 += chunk) {
     const int np = n_pairs - p0 < chunk ? n_pairs - p0 : chunk;
     const int* pl = pair_lib + p0;
     const int* pt = pair_tgt + p0;
+    if (sorted)
+      hipLaunchKernelGGL(ccm::bw_pair_order_kernel, dim3(1), dim3(ccm::kOrderThreads),
+                         (size_t)(n_lib + 1 + ccm::kOrderThreads) * sizeof(int), stream, pl, np,
+                         n_lib, perm);
     hipLaunchKernelGGL(ccm::bw_pair_kernel, dim3(np), dim3(ccm::kBwThreads), (size_t)L * sizeof(float),
                        stream, ts, ld, L, nbr_idx, nbr_w, lib_E, n_lib, k_max, tau, pl, pt,
-                       grad_rho + p0, yhat, H, Gy, pair_ok, ycol);
+                       grad_rho + p0, yhat, H, Gy, pair_ok, ycol, pord);
     const int64_t rows = (int64_t)np * L;
     hipLaunchKernelGGL(ccm::bw_coef_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, stream,
                        ts, ld, L, lib_ts, nbr_idx, lib_E, k_max, tau, pl, pt, np, H, pair_ok, csr_pos,
-                       ycol, com, coT);
+                       ycol, com, coT, pord);
     hipLaunchKernelGGL(ccm::bw_scatter_kernel, dim3((L + 255) / 256, np), dim3(256),
                        (size_t)2 * L * sizeof(float), stream, ts, ld, L, lib_ts, lib_E, k_max, tau,
-                       pl, np, H, Gy, pair_ok, com, coT, csr_off, csr_ent, csr_w, idx_m, tc, lc);
+                       pl, np, H, Gy, pair_ok, com, coT, csr_off, csr_ent, csr_w, idx_m, tc, lc,
+                       pord);
     hipLaunchKernelGGL(ccm::bw_reduce_kernel, dim3((L + ccm::kWave - 1) / ccm::kWave, ccm::kRedHash),
                        dim3(ccm::kWave), 0, stream, ld, L, pl, pt, np, pair_ok, tc, lc, grad_ts,
                        grad_lib);
