@@ -94,7 +94,7 @@ def test_ratenet1024_whole_matrix(ccm):
     L, N = ts.shape
     sha = hashlib.sha256(np.ascontiguousarray(ts, dtype=np.float32).tobytes()).hexdigest()
     assert sha == gold["panel_sha256"], ("the 1,024-series input generator changed: rerun "
-                                         "tests/golden/make_ratenet1024_optE.py")
+                                         "tests/golden/make_optE_golden.py ratenet1024")
     oE = np.asarray(gold["optE"], dtype=np.int32)
     oR = np.array([[np.nan if v is None else v for v in row] for row in gold["rho_E"]])
     d = torch.as_tensor(ts).cuda()
