@@ -111,14 +111,22 @@ __device__ __forceinline__ void lag_values(const float* x, int sc, int tau, floa
 // Build a sorted list from the distinct candidate keys in lanes 0..k1 (~0 where empty): an
 // empty entry becomes ~0 - lane, so all k1 + 1 keys differ and stay above every real key
 // (their index reads negative); a key's rank among them is its lane in the list, and a
-// forward permute moves it there.  Lanes past k1 read ~0.
+// forward permute moves it there.  Lanes past k1 read ~0.  The keys pass through a
+// per-wave LDS row and every lane reads them back at uniform addresses (broadcast reads):
+// one compare per key instead of two lane reads and a compare.  A wave's LDS operations
+// complete in program order, so its reads see its own writes.
+constexpr int kMaxWaves = 16;
+
 __device__ __forceinline__ void list_from_keys(uint64_t cand, int k1, uint64_t& key,
                                                uint64_t& thr) {
+  __shared__ uint64_t rank_keys[kMaxWaves][32];
   const int lane = lane_id();
   const bool mine = lane <= k1;
   const uint64_t v = !mine ? ~0ull : (cand == ~0ull ? ~0ull - (uint64_t)lane : cand);
+  uint64_t* rk = rank_keys[__builtin_amdgcn_readfirstlane(threadIdx.x / kWave)];
+  if (lane < 32) rk[lane] = v;
   int rank = 0;
-  for (int j = 0; j <= k1; ++j) rank += readlane(v, j) < v ? 1 : 0;
+  for (int j = 0; j <= k1; ++j) rank += rk[j] < v ? 1 : 0;
   const int dst = (mine ? rank : lane) << 2;
   const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_permute(dst, (int)(uint32_t)v);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_permute(dst, (int)(uint32_t)(v >> 32));
