@@ -39,6 +39,21 @@
 namespace ccm {
 
 constexpr int kBwThreads = 256;
+constexpr int kXcdA = 8;   // XCDs: workgroup b of a launch runs on XCD b mod 8
+
+// XCD-aware placement of a chunk's pairs: XCD x takes the x-th eighth of the pairs in
+// processing order (pairs of one library are adjacent there), and the nb workgroups of one
+// pair (its blocks of time indices) all land on that XCD, so a pair's buffers and its
+// library's table and lists are read through one L2.  Grid = 8 * ceil(np / 8) * nb
+// workgroups; returns false for the spare ones.
+__device__ __forceinline__ bool xcd_pair_block(int b, int np, int nb, int& slot, int& tb) {
+  const int per = (np + kXcdA - 1) / kXcdA;
+  const int x = b % kXcdA, q = b / kXcdA;
+  const int r = q / nb;
+  tb = q % nb;
+  slot = x * per + r;
+  return r < per && slot < np;
+}
 
 __device__ __forceinline__ double block_sum(double v, double* red) {
   v = wave_sum(v);
@@ -58,10 +73,12 @@ __global__ __launch_bounds__(kBwThreads) void bw_pair_kernel(
     const int* __restrict__ pair_lib, const int* __restrict__ pair_tgt,
     const float* __restrict__ grad_rho, float* __restrict__ yhat, float* __restrict__ H,
     float* __restrict__ Gy, int* __restrict__ pair_ok, float* __restrict__ ycol,
-    const int* __restrict__ perm) {
+    const int* __restrict__ perm, int n_pairs) {
   __shared__ double red[kBwThreads / kWave];
   extern __shared__ float yl[];   // the pair's target column, [L]
-  const int p = perm ? perm[blockIdx.x] : blockIdx.x;
+  int slot, tb;
+  if (!xcd_pair_block(blockIdx.x, n_pairs, 1, slot, tb)) return;   // whole workgroup
+  const int p = perm ? perm[slot] : slot;
   const int i = pair_lib[p];
   const int j = pair_tgt[p];
   const int E = (i >= 0 && i < n_lib) ? lib_E[i] : 0;
@@ -201,10 +218,11 @@ __global__ __launch_bounds__(256) void bw_coef_kernel(
     const float* __restrict__ H, const int* __restrict__ pair_ok, const int* __restrict__ csr_pos,
     const float* __restrict__ ycol, float* __restrict__ com, float* __restrict__ coT,
     const int* __restrict__ perm) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= (int64_t)n_pairs * L) return;
-  const int p = perm ? perm[(int)(g / L)] : (int)(g / L);
-  const int t = (int)(g % L);
+  int slot, tb;
+  if (!xcd_pair_block(blockIdx.x, n_pairs, (L + 255) / 256, slot, tb)) return;
+  const int t = tb * 256 + threadIdx.x;
+  if (t >= L) return;
+  const int p = perm ? perm[slot] : slot;
   float* cm_out = com + (size_t)p * k_max * L + t;     // stride L between m
   const int i = pair_lib[p];
   const int E = pair_ok[p] ? lib_E[i] : 0;
@@ -316,8 +334,10 @@ __global__ __launch_bounds__(256) void bw_scatter_kernel(
     const int* __restrict__ idx_m, float* __restrict__ tc, float* __restrict__ lc,
     const int* __restrict__ perm) {
   extern __shared__ float sm[];   // the library series [L], then the pair's H [L]
-  const int p = perm ? perm[blockIdx.y] : blockIdx.y;
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  int slot, tb;
+  if (!xcd_pair_block(blockIdx.x, n_pairs, (L + 255) / 256, slot, tb)) return;   // whole workgroup
+  const int p = perm ? perm[slot] : slot;
+  const int s = tb * blockDim.x + threadIdx.x;
   float* tco = tc + (size_t)p * L;
   float* lco = lc + (size_t)p * L;
   if (!pair_ok[p]) {   // the whole workgroup
@@ -548,14 +568,16 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
       hipLaunchKernelGGL(ccm::bw_pair_order_kernel, dim3(1), dim3(ccm::kOrderThreads),
                          (size_t)(n_lib + 1 + ccm::kOrderThreads) * sizeof(int), stream, pl, np,
                          n_lib, perm);
-    hipLaunchKernelGGL(ccm::bw_pair_kernel, dim3(np), dim3(ccm::kBwThreads), (size_t)L * sizeof(float),
+    // XCD-aware grids (xcd_pair_block): 8 * ceil(np / 8) slots, times the time blocks
+    const unsigned slots = (unsigned)((np + ccm::kXcdA - 1) / ccm::kXcdA * ccm::kXcdA);
+    const unsigned tblocks = (unsigned)((L + 255) / 256);
+    hipLaunchKernelGGL(ccm::bw_pair_kernel, dim3(slots), dim3(ccm::kBwThreads), (size_t)L * sizeof(float),
                        stream, ts, ld, L, nbr_idx, nbr_w, lib_E, n_lib, k_max, tau, pl, pt,
-                       grad_rho + p0, yhat, H, Gy, pair_ok, ycol, pord);
-    const int64_t rows = (int64_t)np * L;
-    hipLaunchKernelGGL(ccm::bw_coef_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, stream,
+                       grad_rho + p0, yhat, H, Gy, pair_ok, ycol, pord, np);
+    hipLaunchKernelGGL(ccm::bw_coef_kernel, dim3(slots * tblocks), dim3(256), 0, stream,
                        ts, ld, L, lib_ts, nbr_idx, lib_E, k_max, tau, pl, pt, np, H, pair_ok, csr_pos,
                        ycol, com, coT, pord);
-    hipLaunchKernelGGL(ccm::bw_scatter_kernel, dim3((L + 255) / 256, np), dim3(256),
+    hipLaunchKernelGGL(ccm::bw_scatter_kernel, dim3(slots * tblocks), dim3(256),
                        (size_t)2 * L * sizeof(float), stream, ts, ld, L, lib_ts, lib_E, k_max, tau,
                        pl, np, H, Gy, pair_ok, com, coT, csr_off, csr_ent, csr_w, idx_m, tc, lc,
                        pord);
