@@ -239,9 +239,10 @@ ccm_status ccm_crossmap_rho_target_E(const float* ts, int64_t ld, int32_t L,
  *   The tables' rows must hold distinct neighbours (as ccm_knn writes them).  Padding entries
  *   (index -1, as in rows of a subsampled table) count as absent: no weight, no distance.
  *   Any n_pairs >= 0 is accepted: pairs run in chunks (at most 65,535 pairs and at most
- *   2 GiB of per-pair buffers each, 6 L + 2 L k_max floats per pair), one after another in
- *   pair order, so the result does not depend on the chunk size and the workspace stays
- *   bounded (about 2 GiB plus 16 n_lib L k_max bytes for the per-library lists).
+ *   4 GiB of per-pair buffers each, 6 L + 2 L k_max floats and 21 L doubles per pair), one
+ *   after another in pair order, so the result does not depend on the chunk size and the
+ *   workspace stays bounded (about 4 GiB plus 16 n_lib L k_max bytes for the per-library
+ *   lists).
  * Errors: EINVAL, ERANGE, EWORKSPACE.  Workspace: ccm_workspace_size(CCM_OP_CROSSMAP_BACKWARD,
  * L, n_lib, n_pairs, k_max).
  */

@@ -16,7 +16,7 @@
 //            dL/dx(t - e tau) += coef (x(t-e tau) - x(n_m - e tau))
 //            dL/dx(n_m - e tau) -= coef (x(t-e tau) - x(n_m - e tau))
 //
-// gfx950 design: no atomics, fixed summation order (deterministic results).
+// gfx950 design: no atomics on values, fixed summation order (deterministic results).
 //   Kernel 3 (first): one workgroup per library builds the transposed neighbour relation
 //   (for each time s, the table entries whose neighbour is s, in table order), the position
 //   of every entry in it, the weights in that order, and an m-major copy of the table.
@@ -24,11 +24,13 @@
 //   contiguous copy for kernel 2), recomputes yhat and the FP64 Pearson pieces and stores
 //   H, Gy.  Kernel 2: one thread per (pair, t) turns wbar into distance coefficients
 //   (distances recomputed in FP64 from the library series), written m-major and in the
-//   transposed order.  Kernel 4: one thread per (pair, s) gathers everything that lands on
-//   time s, O(E k) per (pair, s): the query side reads m-major rows (consecutive s in
-//   consecutive lanes), the neighbour side reads the transposed lists, whose coefficients
-//   and weights are contiguous.  Kernel 5: one wave per (64 times, column hash) adds the
-//   pairs' contributions in pair order into the target and library gradients.
+//   transposed order.  Kernel 4, in two steps: one thread per (pair, u) reads table row u
+//   (m-major, consecutive u in consecutive lanes) and u's transposed list (coefficients
+//   and weights contiguous) once and keeps E partial sums, one per lag; one thread per
+//   (pair, s) then combines the E + 1 partial sums that land on time s.  Kernel 5: one wave
+//   per (64 times, column hash) adds the pairs' contributions in pair order into the target
+//   and library gradients.
+//   The per-pair kernels run on XCD-aware grids (xcd_pair_block), pairs grouped by library.
 // Padding entries (-1) count as absent everywhere.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -252,7 +254,6 @@ __global__ __launch_bounds__(256) void bw_coef_kernel(
   }
 }
 
-// Contributions of pair p to time s: target (tc) and library (lc).  One thread per (p, s).
 // Transposed neighbour relation of each library's table: for every time s, the entries
 // (t, m) with n_m(t) = s, in increasing (t, m) order, packed as t * 32 + m.  Counts and
 // offsets in LDS; one wave then walks the rows in order (the k neighbours of a row are
@@ -325,31 +326,69 @@ __global__ __launch_bounds__(kTrThreads) void bw_transpose_kernel(
   }
 }
 
-__global__ __launch_bounds__(256) void bw_scatter_kernel(
-    const float* __restrict__ ts, int64_t ld, int L, const float* __restrict__ lib_ts,
-    const int* __restrict__ lib_E, int k_max, int tau, const int* __restrict__ pair_lib,
-    int n_pairs, const float* __restrict__ H, const float* __restrict__ Gy,
+// Everything that lands on time s, in two steps.  For time u, lag e and s = u - e tau:
+//   R(u, e) = sum_m c[u][m] (x(s) - x(n_m(u) - e tau))              (u as a query row, u >= lo)
+//           - sum_q c(q) (x(t_q - e tau) - x(s))                     (u as a neighbour: the
+//                                                                     entries q = (t_q, m) of
+//                                                                     u's transposed list)
+//   TT(u)   = sum_q w(q) H(t_q)
+// The library gradient at s is sum_e R(s + e tau, e) and the target gradient is
+// Gy(s) + TT(s): the same terms as summing over the rows and lists that reach s, each
+// difference formed before its product as there.  Step one (bw_rows_kernel) reads table row
+// u and u's list once and keeps the E partial sums in FP64 registers; step two
+// (bw_sum_kernel) adds the E of them that land on s.  Every row and list was read E times
+// (once per s that needs it) when each s gathered for itself.
+template <int E>
+__device__ __forceinline__ void rows_at(const float* x, const float* hp, int u, int L, int lo,
+                                        int tau, const float* cm, const int* im, const int* off,
+                                        const int* ent, const float* cw, const float* cT,
+                                        double* sr) {
+  constexpr int K = E + 1;
+  double TT = 0.0, R[E], xs[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    R[e] = 0.0;
+    const int s = u - e * tau;   // the time this lag of u lands on (none if negative)
+    xs[e] = s >= 0 ? (double)x[s] : 0.0;
+  }
+  if (u >= lo) {   // u as a query row (then u - e tau >= 0 for every e < E)
+#pragma unroll 1
+    for (int m = 0; m < K; ++m) {
+      const int n = im[(size_t)m * L + u];
+      if (n < 0) continue;   // padding
+      const double c = cm[(size_t)m * L + u];
+#pragma unroll
+      for (int e = 0; e < E; ++e) R[e] += c * (xs[e] - (double)x[n - e * tau]);
+    }
+  }
+  for (int q = off[u]; q < off[u + 1]; ++q) {   // u as a neighbour
+    const int v = ent[q];
+    const int t = v >> 5, m = v & 31;
+    if (t < lo || t >= L || m >= K) continue;   // only a malformed table (repeated neighbours)
+    const double c = cT[q];
+    TT += (double)cw[q] * (double)hp[t];
+#pragma unroll
+    for (int e = 0; e < E; ++e) R[e] -= c * ((double)x[t - e * tau] - xs[e]);
+  }
+  sr[0] = TT;
+#pragma unroll
+  for (int e = 0; e < E; ++e) sr[(size_t)(1 + e) * L] = R[e];
+}
+
+// Step one: one thread per (pair, u); writes TT(u), R(u, e) to sr[p][0 | 1 + e][u] (FP64).
+__global__ __launch_bounds__(256) void bw_rows_kernel(
+    int L, const float* __restrict__ lib_ts, const int* __restrict__ lib_E, int k_max, int tau,
+    const int* __restrict__ pair_lib, int n_pairs, const float* __restrict__ H,
     const int* __restrict__ pair_ok, const float* __restrict__ com, const float* __restrict__ coT,
     const int* __restrict__ csr_off, const int* __restrict__ csr_ent, const float* __restrict__ csr_w,
-    const int* __restrict__ idx_m, float* __restrict__ tc, float* __restrict__ lc,
-    const int* __restrict__ perm) {
+    const int* __restrict__ idx_m, double* __restrict__ srb, const int* __restrict__ perm) {
   extern __shared__ float sm[];   // the library series [L], then the pair's H [L]
   int slot, tb;
   if (!xcd_pair_block(blockIdx.x, n_pairs, (L + 255) / 256, slot, tb)) return;   // whole workgroup
   const int p = perm ? perm[slot] : slot;
-  const int s = tb * blockDim.x + threadIdx.x;
-  float* tco = tc + (size_t)p * L;
-  float* lco = lc + (size_t)p * L;
-  if (!pair_ok[p]) {   // the whole workgroup
-    if (s < L) {
-      tco[s] = 0.0f;
-      lco[s] = 0.0f;
-    }
-    return;
-  }
+  if (!pair_ok[p]) return;   // the whole workgroup: the second step writes zeros
   const int i = pair_lib[p];
   const int E = lib_E[i];
-  const int k = E + 1;
   const int lo = (E - 1) * tau;
   // the series and H are read at scattered times: from LDS
   float* x = sm;
@@ -359,38 +398,54 @@ __global__ __launch_bounds__(256) void bw_scatter_kernel(
     hp[q] = H[(size_t)p * L + q];
   }
   __syncthreads();
-  if (s >= L) return;
+  const int u = tb * blockDim.x + threadIdx.x;
+  if (u >= L) return;
   const float* cm = com + (size_t)p * k_max * L;       // [m][t]
   const float* cT = coT + (size_t)p * L * k_max;       // transposed order
   const int* im = idx_m + (size_t)i * k_max * L;       // [m][t]
   const int* off = csr_off + (size_t)i * (L + 1);
   const int* ent = csr_ent + (size_t)i * L * k_max;
   const float* cw = csr_w + (size_t)i * L * k_max;
-  const double xs = x[s];
-  double T = s >= lo ? (double)Gy[(size_t)p * L + s] : 0.0;
+  double* sr = srb + (size_t)p * (kEMax + 1) * L + u;
+  switch (E) {   // pair_ok guarantees 1 <= E <= 20
+#define CCM_E(EE) \
+  case EE: rows_at<EE>(x, hp, u, L, lo, tau, cm, im, off, ent, cw, cT, sr); break;
+    CCM_E(1) CCM_E(2) CCM_E(3) CCM_E(4) CCM_E(5) CCM_E(6) CCM_E(7) CCM_E(8) CCM_E(9) CCM_E(10)
+    CCM_E(11) CCM_E(12) CCM_E(13) CCM_E(14) CCM_E(15) CCM_E(16) CCM_E(17) CCM_E(18) CCM_E(19)
+    CCM_E(20)
+#undef CCM_E
+    default: break;
+  }
+}
+
+// Step two: one thread per (pair, s): tc[p][s] = Gy(s) + TT(s) (target), lc[p][s] =
+// sum_e R(s + e tau, e) (library); zeros for a pair whose rho is NaN.
+__global__ __launch_bounds__(256) void bw_sum_kernel(
+    int L, const int* __restrict__ lib_E, int tau, const int* __restrict__ pair_lib, int n_pairs,
+    const float* __restrict__ Gy, const int* __restrict__ pair_ok, const double* __restrict__ srb,
+    float* __restrict__ tc, float* __restrict__ lc, const int* __restrict__ perm) {
+  int slot, tb;
+  if (!xcd_pair_block(blockIdx.x, n_pairs, (L + 255) / 256, slot, tb)) return;
+  const int p = perm ? perm[slot] : slot;
+  const int s = tb * blockDim.x + threadIdx.x;
+  if (s >= L) return;
+  float* tco = tc + (size_t)p * L;
+  float* lco = lc + (size_t)p * L;
+  if (!pair_ok[p]) {
+    tco[s] = 0.0f;
+    lco[s] = 0.0f;
+    return;
+  }
+  const int E = lib_E[pair_lib[p]];
+  const int lo = (E - 1) * tau;
+  const double* sr = srb + (size_t)p * (kEMax + 1) * L;
   double Lb = 0.0;
-  // s as lag coordinate e of query t = s + e tau
   for (int e = 0; e < E; ++e) {
-    const int t = s + e * tau;
-    if (t < lo || t >= L) continue;
-    for (int m = 0; m < k; ++m) {
-      const int n = im[(size_t)m * L + t];
-      if (n >= 0) Lb += (double)cm[(size_t)m * L + t] * (xs - (double)x[n - e * tau]);
-    }
+    const int u = s + e * tau;
+    if (u >= L) break;
+    Lb += sr[(size_t)(1 + e) * L + u];
   }
-  // s as a neighbour (the looked-up target value; lag 0 of the neighbour's point) and as
-  // lag coordinate e >= 1 of a neighbour n = s + e tau: the transposed lists of s + e tau
-  for (int e = 0; e < E; ++e) {
-    const int n = s + e * tau;
-    if (n >= L) break;
-    for (int q = off[n]; q < off[n + 1]; ++q) {
-      const int v = ent[q];
-      const int t = v >> 5, m = v & 31;
-      if (t < lo || t >= L || m >= k) continue;   // only a malformed table (repeated neighbours)
-      if (e == 0) T += (double)cw[q] * (double)hp[t];
-      Lb -= (double)cT[q] * ((double)x[t - e * tau] - xs);
-    }
-  }
+  const double T = (s >= lo ? (double)Gy[(size_t)p * L + s] : 0.0) + sr[s];
   tco[s] = (float)T;
   lco[s] = (float)Lb;
 }
@@ -484,13 +539,13 @@ __global__ __launch_bounds__(kWave) void bw_reduce_kernel(
 
 static size_t up256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Pairs are processed in chunks whose per-pair buffers fit in 2 GiB (and whose count fits in
-// grid.y of the scatter kernel).  Chunks run in pair order and each adds its pairs into the
+// Pairs are processed in chunks whose per-pair buffers fit in 4 GiB (and of at most 65,535
+// pairs).  Chunks run in pair order and each adds its pairs into the
 // gradients in pair order, so the result does not depend on the chunk size.
-static constexpr size_t kBwChunkBytes = (size_t)2 << 30;
+static constexpr size_t kBwChunkBytes = (size_t)4 << 30;
 
 static size_t bw_pair_bytes(int L, int k_max) {
-  return 6 * (size_t)L * 4 + 2 * (size_t)L * k_max * 4 + 8;
+  return 6 * (size_t)L * 4 + 2 * (size_t)L * k_max * 4 + (size_t)(ccm::kEMax + 1) * L * 8 + 8;
 }
 
 extern "C" int ccm_backward_chunk_pairs(int L, int k_max) {
@@ -503,15 +558,16 @@ extern "C" int ccm_backward_chunk_pairs(int L, int k_max) {
 extern "C" size_t ccm_backward_ws_bytes(int L, int n_lib, int n_pairs, int k_max) {
   // per pair of a chunk: yhat, H, Gy, tc, lc, the target column ([P][L] floats each), the
   // coefficients twice ([P][k_max][L] and [P][L k_max] floats), pair_ok and the processing
-  // order ([P] ints each); per library: CSR offsets [L + 1], entries, positions, weights and
-  // the m-major table copy, [L k_max] each
+  // order ([P] ints each), the per-time partial sums ([P][21][L] doubles); per library: CSR
+  // offsets [L + 1], entries, positions, weights and the m-major table copy, [L k_max] each
   const int chunk = ccm_backward_chunk_pairs(L, k_max);
   const size_t P = (size_t)(n_pairs < chunk ? n_pairs : chunk);
   const size_t a = up256(P * L * 4);
   const size_t c = up256(P * L * k_max * 4);
   const size_t t = up256((size_t)n_lib * L * k_max * 4);
   return 6 * a + 2 * c + up256(P * 4) + up256((size_t)n_lib * (L + 1) * 4) + 4 * t +
-         up256(P * 4);   // the pairs' processing order
+         up256(P * 4) +                                  // the pairs' processing order
+         up256(P * (ccm::kEMax + 1) * L * 8);            // per-time partial sums (FP64)
 }
 
 extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, const float* lib_ts,
@@ -543,6 +599,7 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
   float* csr_w = (float*)((char*)csr_pos + tb);
   int* idx_m = (int*)((char*)csr_w + tb);
   int* perm = (int*)((char*)idx_m + tb);
+  double* srb = (double*)((char*)perm + up256(P * 4));
   static std::atomic<uint64_t> attr{0};
   hipError_t e = ccm::allow_lds_once((const void*)ccm::bw_transpose_kernel, attr);
   if (e != hipSuccess) return e;
@@ -552,8 +609,8 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
   static std::atomic<uint64_t> attr_pair{0};
   e = ccm::allow_lds_once((const void*)ccm::bw_pair_kernel, attr_pair);
   if (e != hipSuccess) return e;
-  static std::atomic<uint64_t> attr_scatter{0};
-  e = ccm::allow_lds_once((const void*)ccm::bw_scatter_kernel, attr_scatter);
+  static std::atomic<uint64_t> attr_rows{0};
+  e = ccm::allow_lds_once((const void*)ccm::bw_rows_kernel, attr_rows);
   if (e != hipSuccess) return e;
   static std::atomic<uint64_t> attr_order{0};
   e = ccm::allow_lds_once((const void*)ccm::bw_pair_order_kernel, attr_order);
@@ -577,10 +634,11 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
     hipLaunchKernelGGL(ccm::bw_coef_kernel, dim3(slots * tblocks), dim3(256), 0, stream,
                        ts, ld, L, lib_ts, nbr_idx, lib_E, k_max, tau, pl, pt, np, H, pair_ok, csr_pos,
                        ycol, com, coT, pord);
-    hipLaunchKernelGGL(ccm::bw_scatter_kernel, dim3(slots * tblocks), dim3(256),
-                       (size_t)2 * L * sizeof(float), stream, ts, ld, L, lib_ts, lib_E, k_max, tau,
-                       pl, np, H, Gy, pair_ok, com, coT, csr_off, csr_ent, csr_w, idx_m, tc, lc,
-                       pord);
+    hipLaunchKernelGGL(ccm::bw_rows_kernel, dim3(slots * tblocks), dim3(256),
+                       (size_t)2 * L * sizeof(float), stream, L, lib_ts, lib_E, k_max, tau, pl, np,
+                       H, pair_ok, com, coT, csr_off, csr_ent, csr_w, idx_m, srb, pord);
+    hipLaunchKernelGGL(ccm::bw_sum_kernel, dim3(slots * tblocks), dim3(256), 0, stream, L, lib_E,
+                       tau, pl, np, Gy, pair_ok, srb, tc, lc, pord);
     hipLaunchKernelGGL(ccm::bw_reduce_kernel, dim3((L + ccm::kWave - 1) / ccm::kWave, ccm::kRedHash),
                        dim3(ccm::kWave), 0, stream, ld, L, pl, pt, np, pair_ok, tc, lc, grad_ts,
                        grad_lib);

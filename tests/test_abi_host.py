@@ -170,21 +170,21 @@ def test_matrix_argument_errors_before_device_work():
 
 def test_backward_workspace_is_bounded_by_chunks():
     # pairs run in chunks: the workspace stops growing once a chunk is full, and a chunk
-    # never exceeds 65,535 pairs (grid.y of the scatter kernel) or 2 GiB of per-pair buffers
+    # never exceeds 65,535 pairs or 4 GiB of per-pair buffers
     lib = ccm.load_library()
     lib.ccm_backward_chunk_pairs.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.ccm_backward_chunk_pairs.restype = ctypes.c_int32
     for L, k_max in ((1600, 21), (100, 3), (16384, 21), (8, 2)):
         c = lib.ccm_backward_chunk_pairs(L, k_max)
-        per = 6 * L * 4 + 2 * L * k_max * 4 + 4
-        assert 1 <= c <= 65535 and c * per <= 2 << 30
+        per = 6 * L * 4 + 2 * L * k_max * 4 + 21 * L * 8 + 8
+        assert 1 <= c <= 65535 and c * per <= 4 << 30
         at_chunk = ccm.workspace_size(ccm.OP_CROSSMAP_BACKWARD, L, 64, c, k_max)
         assert ccm.workspace_size(ccm.OP_CROSSMAP_BACKWARD, L, 64, 2_000_000_000, k_max) == at_chunk
         assert ccm.workspace_size(ccm.OP_CROSSMAP_BACKWARD, L, 64, max(c - 1, 0), k_max) <= at_chunk
-    # 52 M pairs (a dense rho.sum() over a 512 x 101,729 block) at L = 1600: about 2 GiB plus
+    # 52 M pairs (a dense rho.sum() over a 512 x 101,729 block) at L = 1600: about 4 GiB plus
     # the per-library lists
     n = ccm.workspace_size(ccm.OP_CROSSMAP_BACKWARD, 1600, 512, 512 * 101729, 21)
-    assert n < (2 << 30) + 16 * 512 * 1601 * 21 + 4 * 512 * 1601 + (1 << 20)
+    assert n < (4 << 30) + 16 * 512 * 1601 * 21 + 4 * 512 * 1601 + (1 << 20)
 
 
 def test_storage_span_check():
