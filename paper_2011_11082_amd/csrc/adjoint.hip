@@ -157,33 +157,39 @@ __global__ __launch_bounds__(kBwThreads) void bw_pair_kernel(
 
 // coef = dbar_m / d_m (0 for zero distances), one thread per (pair, t), written twice: m-major
 // (com[p][m][t], read by the query side) and in the library's transposed order (coT[p][q] at
-// q = pos[t][m], read by the neighbour side).
+// q = pos[m][t], read by the neighbour side).  Only entries that step reads are written: rows
+// t >= (E-1) tau, m < E + 1, pairs with a finite rho.
 // One row's coefficients at a compile-time k = E + 1, so the per-neighbour FP64 distances
-// and kernel values stay in registers (the weighted target h y(n_m) is re-read).
+// and kernel values stay in registers (the weighted target h y(n_m) is re-read).  The table
+// row and its list positions are read m-major (stride L), so consecutive t in consecutive
+// lanes read contiguous runs; the library series and the target column sit in LDS.
 __device__ __forceinline__ double coef_wb(const float* yc, int nb, double h) {
   return nb < 0 ? 0.0 : h * (double)yc[nb];
 }
 template <int K>
-__device__ __forceinline__ void coef_row(const float* x, const float* yc, const int* ri,
-                                         const int* pos, int t, int tau, double h, int k_max,
-                                         int L, float* cm_out, float* cT) {
+__device__ __forceinline__ void coef_row(const float* x, const float* yc, const int* im,
+                                         const int* pm, int t, int tau, double h, int L,
+                                         float* cm_out, float* cT) {
   constexpr int E = K - 1;
+  int ri[K];
   double d[K], u[K];
 #pragma unroll
-  for (int m = 0; m < K; ++m) {
-    const int nb = ri[m];
-    if (nb < 0) {   // padding entry: weight 0, no distance
-      d[m] = INFINITY;
-      continue;
-    }
-    double dd = 0.0;
+  for (int m = 0; m < K; ++m) ri[m] = im[(size_t)m * L];
+  // the K distances advance one lag at a time, so the K reads of a lag are independent
+  // (each sum still runs over the lags in order)
+#pragma unroll
+  for (int m = 0; m < K; ++m) d[m] = 0.0;
 #pragma unroll 1
-    for (int e = 0; e < E; ++e) {
-      const double df = (double)x[t - e * tau] - (double)x[nb - e * tau];
-      dd += df * df;
+  for (int e = 0; e < E; ++e) {
+    const double xt = x[t - e * tau];
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      const double df = xt - (double)x[(ri[m] < 0 ? t : ri[m]) - e * tau];
+      d[m] += df * df;
     }
-    d[m] = sqrt(dd);
   }
+#pragma unroll
+  for (int m = 0; m < K; ++m) d[m] = ri[m] < 0 ? INFINITY : sqrt(d[m]);   // padding: no distance
   const double d1 = d[0];
   double S = 0.0;
 #pragma unroll
@@ -205,47 +211,54 @@ __device__ __forceinline__ void coef_row(const float* x, const float* yc, const 
       cm = db / d[m];
     }
     cm_out[(size_t)m * L] = (float)cm;
-    if (ri[m] >= 0 && ri[m] < L) cT[pos[m]] = (float)cm;
+    if (ri[m] >= 0 && ri[m] < L) cT[pm[(size_t)m * L]] = (float)cm;
   }
-  for (int m = K; m < k_max; ++m) cm_out[(size_t)m * L] = 0.0f;
   const float c0 = d1 > 0.0 ? (float)(dbar1 / d1) : 0.0f;
   cm_out[0] = c0;
-  if (ri[0] >= 0 && ri[0] < L) cT[pos[0]] = c0;
+  if (ri[0] >= 0 && ri[0] < L) cT[pm[0]] = c0;
 }
 
 __global__ __launch_bounds__(256) void bw_coef_kernel(
-    const float* __restrict__ ts, int64_t ld, int L, const float* __restrict__ lib_ts,
-    const int* __restrict__ nbr_idx, const int* __restrict__ lib_E, int k_max, int tau,
-    const int* __restrict__ pair_lib, const int* __restrict__ pair_tgt, int n_pairs,
-    const float* __restrict__ H, const int* __restrict__ pair_ok, const int* __restrict__ csr_pos,
+    int L, const float* __restrict__ lib_ts, const int* __restrict__ lib_E, int k_max, int tau,
+    const int* __restrict__ pair_lib, int n_pairs, const float* __restrict__ H,
+    const int* __restrict__ pair_ok, const int* __restrict__ pos_m, const int* __restrict__ idx_m,
     const float* __restrict__ ycol, float* __restrict__ com, float* __restrict__ coT,
     const int* __restrict__ perm) {
+  extern __shared__ float sm[];   // the library series [L], then the target column [L]
   int slot, tb;
-  if (!xcd_pair_block(blockIdx.x, n_pairs, (L + 255) / 256, slot, tb)) return;
-  const int t = tb * 256 + threadIdx.x;
-  if (t >= L) return;
+  if (!xcd_pair_block(blockIdx.x, n_pairs, (L + 255) / 256, slot, tb)) return;   // whole workgroup
   const int p = perm ? perm[slot] : slot;
-  float* cm_out = com + (size_t)p * k_max * L + t;     // stride L between m
+  if (!pair_ok[p]) return;   // whole workgroup: the rows step skips the pair
   const int i = pair_lib[p];
-  const int E = pair_ok[p] ? lib_E[i] : 0;
+  const int E = lib_E[i];   // pair_ok guarantees 1 <= E <= 20 and E + 1 <= k_max
+  const int K = E + 1;
   const int lo = (E - 1) * tau;
-  if (!pair_ok[p] || t < lo) {
-    for (int m = 0; m < k_max; ++m) cm_out[(size_t)m * L] = 0.0f;
-    return;
+  if (tb * 256 + 255 < lo) return;   // whole workgroup: no query row in this block
+  float* x = sm;
+  float* yc = sm + L;
+  for (int q = threadIdx.x; q < L; q += blockDim.x) {
+    x[q] = lib_ts[(size_t)i * L + q];
+    yc[q] = ycol[(size_t)p * L + q];
   }
-  const int* pos = csr_pos + ((size_t)i * L + t) * k_max;
-  float* cT = coT + (size_t)p * L * k_max;
-  const float* yc = ycol + (size_t)p * L;   // the pair's target column
-  const float* x = lib_ts + (size_t)i * L;
-  const int* ri = nbr_idx + ((size_t)i * L + t) * k_max;
+  __syncthreads();
+  const int t = tb * 256 + threadIdx.x;
+  if (t >= L || t < lo) return;
+  const int* im = idx_m + (size_t)i * k_max * L + t;   // [m][t]
+  const int* pm = pos_m + (size_t)i * k_max * L + t;   // [m][t]
+  float* cm_out = com + (size_t)p * k_max * L + t;     // [m][t]
+  float* cT = coT + (size_t)p * L * k_max;             // transposed order
   const double h = H[(size_t)p * L + t];
-  if (ri[0] < 0) {   // a row of padding only (a subsampled table): no contribution
-    for (int m = 0; m < k_max; ++m) cm_out[(size_t)m * L] = 0.0f;
+  if (im[0] < 0) {   // a row of padding (a subsampled table): no contribution
+    for (int m = 0; m < K; ++m) {
+      cm_out[(size_t)m * L] = 0.0f;
+      const int nb = im[(size_t)m * L];
+      if (nb >= 0 && nb < L) cT[pm[(size_t)m * L]] = 0.0f;
+    }
     return;
   }
-  switch (E) {   // pair_ok guarantees 1 <= E <= 20 and E + 1 <= k_max
+  switch (E) {
 #define CCM_K(EE) \
-  case EE: coef_row<EE + 1>(x, yc, ri, pos, t, tau, h, k_max, L, cm_out, cT); break;
+  case EE: coef_row<EE + 1>(x, yc, im, pm, t, tau, h, L, cm_out, cT); break;
     CCM_K(1) CCM_K(2) CCM_K(3) CCM_K(4) CCM_K(5) CCM_K(6) CCM_K(7) CCM_K(8) CCM_K(9) CCM_K(10)
     CCM_K(11) CCM_K(12) CCM_K(13) CCM_K(14) CCM_K(15) CCM_K(16) CCM_K(17) CCM_K(18) CCM_K(19)
     CCM_K(20)
@@ -258,12 +271,17 @@ __global__ __launch_bounds__(256) void bw_coef_kernel(
 // (t, m) with n_m(t) = s, in increasing (t, m) order, packed as t * 32 + m.  Counts and
 // offsets in LDS; one wave then walks the rows in order (the k neighbours of a row are
 // distinct, so its lanes never write the same list), which keeps the order deterministic.
+// The walk loads kTrRows rows at a time before placing them, so one load latency is paid
+// per group of rows rather than per row.  Also written: each entry's list position and an
+// m-major copy of the table ([m][t] each, rows t >= (E-1) tau, m < k), and the weights in
+// list order.
 constexpr int kTrThreads = 256;
+constexpr int kTrRows = 16;
 
 __global__ __launch_bounds__(kTrThreads) void bw_transpose_kernel(
     const int* __restrict__ nbr_idx, const float* __restrict__ nbr_w, const int* __restrict__ lib_E,
     int L, int k_max, int tau, int* __restrict__ csr_off, int* __restrict__ csr_ent,
-    int* __restrict__ csr_pos, float* __restrict__ csr_w, int* __restrict__ idx_m) {
+    int* __restrict__ pos_m, float* __restrict__ csr_w, int* __restrict__ idx_m) {
   extern __shared__ int cnt[];          // [L + 1], then chunk sums [kTrThreads]
   int* csum = cnt + L + 1;
   const int i = blockIdx.x;
@@ -309,18 +327,29 @@ __global__ __launch_bounds__(kTrThreads) void bw_transpose_kernel(
   for (int q = threadIdx.x; q <= L; q += blockDim.x) off[q] = cnt[q];
   __syncthreads();
   int* ent = csr_ent + (size_t)i * L * k_max;
-  int* pos = csr_pos + (size_t)i * L * k_max;
+  int* pos = pos_m + (size_t)i * k_max * L;
   float* cw = csr_w + (size_t)i * L * k_max;
   const float* wtab = nbr_w + (size_t)i * L * k_max;
   if (threadIdx.x < kWave) {
     const int lane = threadIdx.x;
-    for (int t = lo; t < L; ++t) {
-      const int s = lane < k ? tab[(size_t)t * k_max + lane] : -1;
-      if (s >= 0 && s < L) {
-        const int q = cnt[s]++;
-        ent[q] = t * 32 + lane;
-        pos[(size_t)t * k_max + lane] = q;
-        cw[q] = wtab[(size_t)t * k_max + lane];
+    for (int t0 = lo; t0 < L; t0 += kTrRows) {
+      int sv[kTrRows];
+      float wv[kTrRows];
+#pragma unroll
+      for (int r = 0; r < kTrRows; ++r) {
+        const bool in = lane < k && t0 + r < L;
+        sv[r] = in ? tab[(size_t)(t0 + r) * k_max + lane] : -1;
+        wv[r] = in ? wtab[(size_t)(t0 + r) * k_max + lane] : 0.0f;
+      }
+#pragma unroll
+      for (int r = 0; r < kTrRows; ++r) {
+        const int s = sv[r];
+        if (s >= 0 && s < L) {
+          const int q = cnt[s]++;
+          ent[q] = (t0 + r) * 32 + lane;
+          pos[(size_t)lane * L + t0 + r] = q;
+          cw[q] = wv[r];
+        }
       }
     }
   }
@@ -595,8 +624,8 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
   int* pair_ok = (int*)after_coef;
   int* csr_off = (int*)(after_coef + up256(P * 4));
   int* csr_ent = (int*)((char*)csr_off + up256((size_t)n_lib * (L + 1) * 4));
-  int* csr_pos = (int*)((char*)csr_ent + tb);
-  float* csr_w = (float*)((char*)csr_pos + tb);
+  int* pos_m = (int*)((char*)csr_ent + tb);
+  float* csr_w = (float*)((char*)pos_m + tb);
   int* idx_m = (int*)((char*)csr_w + tb);
   int* perm = (int*)((char*)idx_m + tb);
   double* srb = (double*)((char*)perm + up256(P * 4));
@@ -605,9 +634,12 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(ccm::bw_transpose_kernel, dim3(n_lib), dim3(ccm::kTrThreads),
                      (size_t)(L + 1 + ccm::kTrThreads) * sizeof(int), stream, nbr_idx, nbr_w, lib_E,
-                     L, k_max, tau, csr_off, csr_ent, csr_pos, csr_w, idx_m);
+                     L, k_max, tau, csr_off, csr_ent, pos_m, csr_w, idx_m);
   static std::atomic<uint64_t> attr_pair{0};
   e = ccm::allow_lds_once((const void*)ccm::bw_pair_kernel, attr_pair);
+  if (e != hipSuccess) return e;
+  static std::atomic<uint64_t> attr_coef{0};
+  e = ccm::allow_lds_once((const void*)ccm::bw_coef_kernel, attr_coef);
   if (e != hipSuccess) return e;
   static std::atomic<uint64_t> attr_rows{0};
   e = ccm::allow_lds_once((const void*)ccm::bw_rows_kernel, attr_rows);
@@ -631,9 +663,9 @@ extern "C" hipError_t ccm_launch_backward(const float* ts, int64_t ld, int L, co
     hipLaunchKernelGGL(ccm::bw_pair_kernel, dim3(slots), dim3(ccm::kBwThreads), (size_t)L * sizeof(float),
                        stream, ts, ld, L, nbr_idx, nbr_w, lib_E, n_lib, k_max, tau, pl, pt,
                        grad_rho + p0, yhat, H, Gy, pair_ok, ycol, pord, np);
-    hipLaunchKernelGGL(ccm::bw_coef_kernel, dim3(slots * tblocks), dim3(256), 0, stream,
-                       ts, ld, L, lib_ts, nbr_idx, lib_E, k_max, tau, pl, pt, np, H, pair_ok, csr_pos,
-                       ycol, com, coT, pord);
+    hipLaunchKernelGGL(ccm::bw_coef_kernel, dim3(slots * tblocks), dim3(256),
+                       (size_t)2 * L * sizeof(float), stream, L, lib_ts, lib_E, k_max, tau, pl, np,
+                       H, pair_ok, pos_m, idx_m, ycol, com, coT, pord);
     hipLaunchKernelGGL(ccm::bw_rows_kernel, dim3(slots * tblocks), dim3(256),
                        (size_t)2 * L * sizeof(float), stream, L, lib_ts, lib_E, k_max, tau, pl, np,
                        H, pair_ok, com, coT, csr_off, csr_ent, csr_w, idx_m, srb, pord);
