@@ -134,6 +134,27 @@ __device__ __forceinline__ void list_from_keys(uint64_t cand, int k1, uint64_t& 
   thr = readlane(key, k1);
 }
 
+// Build a sorted list of k1 + 1 entries from the distinct keys of pool lanes 0..np-1 (~0
+// where empty, np <= 64), as list_from_keys does for k1 + 1 keys: every pool key gets its
+// rank among the np keys, and the pool lanes are permuted by rank (a bijection of 0..np-1),
+// so lanes 0..k1 hold the k1 + 1 smallest in order.
+__device__ __forceinline__ void list_from_pool(uint64_t cand, int np, int k1, uint64_t& key,
+                                               uint64_t& thr) {
+  __shared__ uint64_t pool_keys[kMaxWaves][kWave];
+  const int lane = lane_id();
+  const bool mine = lane < np;
+  const uint64_t v = !mine ? ~0ull : (cand == ~0ull ? ~0ull - (uint64_t)lane : cand);
+  uint64_t* rk = pool_keys[__builtin_amdgcn_readfirstlane(threadIdx.x / kWave)];
+  rk[lane] = v;
+  int rank = 0;
+  for (int j = 0; j < np; ++j) rank += rk[j] < v ? 1 : 0;
+  const int dst = (mine ? rank : lane) << 2;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_permute(dst, (int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_permute(dst, (int)(uint32_t)(v >> 32));
+  key = ((uint64_t)hi << 32) | lo;
+  thr = readlane(key, k1);
+}
+
 // The k-th distance of a list as a float bound for a prefilter: +inf while the list is not
 // full (its k-th key is empty), else the d^2 of the k-th key.  A candidate can enter the
 // list only if its d^2 <= this bound.
@@ -371,35 +392,95 @@ __global__ __launch_bounds__(kKnnThreads) __attribute__((amdgpu_waves_per_eu(8, 
 }
 
 // ---------------------------------------------------------------------------------------
-// Simplex projection skill, one workgroup per (series, E group).  Groups are fixed at
-// E = 1..10, 11..16, 17..20 (about equal work: lags grow with E, and so do the lists) and
-// clipped to [E_min, E_max].  The squared distance is accumulated over lags 0..EHI-1 once;
-// each E of the group keeps its own list.  LOO: Q_E = C_E = [(E-1)tau, L-1-Tp], query
-// excluded.  HALF: C_E = [(E-1)tau, h-1-Tp], Q_E = [h+(E-1)tau, L-1-Tp], h = L/2, no
-// exclusion.  Writes the FP64 skill of each E to rho64[series][E-1].
+// Simplex projection skill, one workgroup per (series, E group).  Groups are fixed (the
+// table below) and clipped to [E_min, E_max].  The squared distance is accumulated over lags
+// 0..EHI-1 once; each E of the group keeps its own list.  LOO: Q_E = C_E = [(E-1)tau,
+// L-1-Tp], query excluded.  HALF: C_E = [(E-1)tau, h-1-Tp], Q_E = [h+(E-1)tau, L-1-Tp],
+// h = L/2, no exclusion.  Writes the FP64 skill of each E to rho64[series][E-1].
+// The kernel waits on LDS and on its serial list updates far more than it computes, so the
+// groups are kept small (four lists: about 80 VGPRs) and the kernel runs at kSimplexOcc
+// waves per SIMD even at the cost of a small spill; the lags a group repeats are cheap next
+// to that.
 // ---------------------------------------------------------------------------------------
 constexpr int kSimplexThreads = 512;
-constexpr int kGroupE = 10;
+constexpr int kSimplexOcc = 8;
+// (group, first E, last E); every group holds an even number of lists
+#define CCM_SIMPLEX_GROUPS(X) X(0, 1, 4) X(1, 5, 8) X(2, 9, 12) X(3, 13, 16) X(4, 17, 20)
+constexpr int kNGroups = 5;
+constexpr int kGroupE = 4;   // most lists in a group
+__device__ __forceinline__ int group_lo(int g) {
+#define CCM_LO(G, LO, HI) if (g == G) return LO;
+  CCM_SIMPLEX_GROUPS(CCM_LO)
+#undef CCM_LO
+  return 1;
+}
+__device__ __forceinline__ int group_hi(int g) {
+#define CCM_HI(G, LO, HI) if (g == G) return HI;
+  CCM_SIMPLEX_GROUPS(CCM_HI)
+#undef CCM_HI
+  return 0;
+}
 
 // Seed every list of the group that held a list at the previous query (t - 1 >= its first
-// query) from that list; lists starting at t begin empty.
+// query); lists starting at t begin empty.  List E is seeded from a pool: the previous
+// query's lists of E, E - 1 and E + 1 (those of this group), each neighbour shifted one step
+// forward.  Nearby E share most neighbours, and their union holds more of t's true
+// neighbours than one list does, so the k-th distance starts tighter and the scan inserts
+// fewer candidates.  A neighbour met in two lists enters the pool once (the first lane to
+// set its bit in the wave's LDS bitmap `bm` keeps it; the bits are cleared again at once).
+// `prev` carries the previous list's old index (this query's seeding has overwritten key).
 template <int ELO, int G, int NG, bool TAU1, int EHI>
 __device__ __forceinline__ void seed_group(const float* x, int t, int tau, int chi, bool half,
                                            int qbase, int E_lo, int E_hi,
                                            const float (&xq)[EHI], uint64_t (&key)[NG],
-                                           uint64_t (&thr)[NG]) {
+                                           uint64_t (&thr)[NG], uint32_t* bm, int prev) {
   if constexpr (G < NG) {
     constexpr int E = ELO + G;
+    const int lane = lane_id();
+    const int own = key_idx(key[G]);   // this list's previous entries, before it is reseeded
     const int qE = qbase + (E - 1) * tau;
-    if (E >= E_lo && E <= E_hi && t - 1 >= qE)
-      seed_list<E, TAU1, EHI>(x, nullptr, t, tau, chi, !half, xq, key[G], thr[G]);
-    seed_group<ELO, G + 1, NG, TAU1, EHI>(x, t, tau, chi, half, qbase, E_lo, E_hi, xq, key, thr);
+    if (E >= E_lo && E <= E_hi && t - 1 >= qE) {
+      // pool lanes: [0, E] own entries; then the E entries of list E - 1 (G > 0); then the
+      // E + 2 entries of list E + 1 (G + 1 < NG): at most 3 E + 3 <= 63 lanes
+      constexpr int off_hi = (E + 1) + (G > 0 ? E : 0);
+      constexpr int np = off_hi + (G + 1 < NG ? E + 2 : 0);
+      int nb = lane <= E ? own : -1;
+      if constexpr (G > 0) {
+        const int src = lane - (E + 1);
+        const int v = __builtin_amdgcn_ds_bpermute((src >= 0 ? src : 0) << 2, prev);
+        if (lane > E && lane < off_hi) nb = v;
+      }
+      if constexpr (G + 1 < NG) {
+        const int src = lane - off_hi;
+        const int v = __builtin_amdgcn_ds_bpermute((src >= 0 ? src : 0) << 2, key_idx(key[G + 1]));
+        if (lane >= off_hi && lane < np) nb = v;
+      }
+      const int s = nb + 1;
+      bool ok = nb >= 0 && s <= chi && s >= (E - 1) * tau && (half || s != t);
+      if (ok) {   // keep the first lane holding s
+        const uint32_t bit = 1u << (s & 31);
+        ok = (atomicOr(&bm[s >> 5], bit) & bit) == 0u;
+      }
+      if (nb >= 0 && s <= chi && s >= 0) atomicAnd(&bm[s >> 5], ~(1u << (s & 31)));
+      const int sc = ok ? s : (E - 1) * tau;
+      float xs[E];
+      lag_values<E, TAU1>(x, sc, tau, xs);
+      float acc = 0.0f;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const float df = xq[e] - xs[e];
+        acc = acc + df * df;
+      }
+      list_from_pool(ok ? nkey(acc, s) : ~0ull, np, E, key[G], thr[G]);
+    }
+    seed_group<ELO, G + 1, NG, TAU1, EHI>(x, t, tau, chi, half, qbase, E_lo, E_hi, xq, key, thr,
+                                          bm, own);
   }
 }
 
 template <int ELO, int EHI, bool TAU1>
 __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, int E_max, int tau,
-                                              int Tp, bool half, int wave, int nw,
+                                              int Tp, bool half, int wave, int nw, uint32_t* bm,
                                               double (&wsum)[kSimplexThreads / kWave][kGroupE][5]) {
   constexpr int NG = EHI - ELO + 1;
   const int lane = lane_id();
@@ -433,7 +514,7 @@ __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, 
           __float_as_int(t - e * tau >= 0 ? x[t - e * tau] : 0.0f)));
     const bool seeded = t > tb;
     if (seeded) seed_group<ELO, 0, NG, TAU1, EHI>(x, t, tau, chi, half, qbase, E_lo, E_hi, xq,
-                                                  key, thr);
+                                                  key, thr, bm, -1);
     // prefilter bound per list: -1 for a list not active at t (nothing passes)
     float tf[NG];
 #pragma unroll
@@ -514,39 +595,45 @@ __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, 
   }
 }
 
-__global__ __launch_bounds__(kSimplexThreads) void simplex_kernel(
+__global__ __launch_bounds__(kSimplexThreads) __attribute__((amdgpu_waves_per_eu(kSimplexOcc, kSimplexOcc))) void simplex_kernel(
     const float* __restrict__ ts, int64_t ld, int L, const int* __restrict__ ids, int E_min,
     int E_max, int tau, int Tp, int mode, double* __restrict__ rho64) {
+  // dynamic LDS: the series after kPad zeros, then each wave's bitmap over times (W words)
   extern __shared__ float xbuf[];
   float* x = xbuf + kPad;
   __shared__ double wsum[kSimplexThreads / kWave][kGroupE][5];
-  const int grp = blockIdx.y;
-  const int ELO = grp == 0 ? 1 : (grp == 1 ? 11 : 17);
-  const int EHI = grp == 0 ? 10 : (grp == 1 ? 16 : 20);
+  const int grp = kNGroups - 1 - (int)blockIdx.y;   // the groups of larger E (longer) first
+  const int series = blockIdx.x;
+  const int ELO = group_lo(grp);
+  const int EHI = group_hi(grp);
   const int E_lo = ELO > E_min ? ELO : E_min;
   const int E_hi = EHI < E_max ? EHI : E_max;
   if (E_lo > E_hi) return;  // whole workgroup: group outside [E_min, E_max]
-  const int sid = ids[blockIdx.x];
+  const int sid = ids[series];
   if (sid < 0 || sid >= ld) {   // a series outside the panel: NaN skills, so optE = E_min
     if ((int)threadIdx.x >= E_lo - 1 && (int)threadIdx.x < E_hi)
-      rho64[(size_t)blockIdx.x * kEMax + threadIdx.x] = __builtin_nan("");
+      rho64[(size_t)series * kEMax + threadIdx.x] = __builtin_nan("");
     return;
   }
   for (int t = threadIdx.x; t < L + kPad; t += blockDim.x)
     xbuf[t] = t < kPad ? 0.0f : ts[(int64_t)(t - kPad) * ld + sid];
+  const int W = (L + 31) / 32;
+  for (int w = threadIdx.x; w < W * (int)(blockDim.x / kWave); w += blockDim.x)
+    ((uint32_t*)(xbuf + L + kPad))[w] = 0u;
   __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int nw = blockDim.x / kWave;
+  uint32_t* bm = (uint32_t*)(xbuf + L + kPad) + (size_t)wave * W;
   const bool half = mode == 1;
-  if (grp == 0) {
-    if (tau == 1) simplex_group<1, 10, true>(x, L, E_min, E_max, tau, Tp, half, wave, nw, wsum);
-    else simplex_group<1, 10, false>(x, L, E_min, E_max, tau, Tp, half, wave, nw, wsum);
-  } else if (grp == 1) {
-    if (tau == 1) simplex_group<11, 16, true>(x, L, E_min, E_max, tau, Tp, half, wave, nw, wsum);
-    else simplex_group<11, 16, false>(x, L, E_min, E_max, tau, Tp, half, wave, nw, wsum);
-  } else {
-    if (tau == 1) simplex_group<17, 20, true>(x, L, E_min, E_max, tau, Tp, half, wave, nw, wsum);
-    else simplex_group<17, 20, false>(x, L, E_min, E_max, tau, Tp, half, wave, nw, wsum);
+  switch (grp) {
+#define CCM_RUN(G, LO, HI)                                                                 \
+  case G:                                                                                  \
+    if (tau == 1) simplex_group<LO, HI, true>(x, L, E_min, E_max, tau, Tp, half, wave, nw, bm, wsum); \
+    else simplex_group<LO, HI, false>(x, L, E_min, E_max, tau, Tp, half, wave, nw, bm, wsum);  \
+    break;
+    CCM_SIMPLEX_GROUPS(CCM_RUN)
+#undef CCM_RUN
+    default: break;
   }
   __syncthreads();
   if (threadIdx.x < kGroupE) {
@@ -560,7 +647,7 @@ __global__ __launch_bounds__(kSimplexThreads) void simplex_kernel(
       const int qfirst = qbase + (E - 1) * tau;
       const int qhi = L - 1 - Tp;
       const double n = (double)(qhi - qfirst + 1);
-      rho64[(size_t)blockIdx.x * kEMax + (E - 1)] =
+      rho64[(size_t)series * kEMax + (E - 1)] =
           n > 0 ? pearson_from_moments(n, sm[0], sm[1], sm[2], sm[3], sm[4]) : __builtin_nan("");
     }
   }
@@ -636,8 +723,9 @@ extern "C" hipError_t ccm_launch_simplex(const float* ts, int64_t ld, int L, con
   static std::atomic<uint64_t> attr{0};
   hipError_t e = ccm::allow_lds_once((const void*)ccm::simplex_kernel, attr);
   if (e != hipSuccess) return e;
-  size_t lds = (size_t)(L + ccm::kPad) * sizeof(float);
-  hipLaunchKernelGGL(ccm::simplex_kernel, dim3(n, 3), dim3(ccm::kSimplexThreads), lds, stream, ts,
+  const size_t lds = (size_t)(L + ccm::kPad) * sizeof(float) +
+                     (size_t)(ccm::kSimplexThreads / ccm::kWave) * ((L + 31) / 32) * sizeof(uint32_t);
+  hipLaunchKernelGGL(ccm::simplex_kernel, dim3(n, ccm::kNGroups), dim3(ccm::kSimplexThreads), lds, stream, ts,
                      ld, L, ids, E_min, E_max, tau, Tp, mode, rho64);
   hipLaunchKernelGGL(ccm::simplex_finalize_kernel, dim3((n + 255) / 256), dim3(256), 0, stream,
                      rho64, n, E_min, E_max, optE, rho_E);
