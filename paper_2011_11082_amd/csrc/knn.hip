@@ -402,7 +402,10 @@ __global__ __launch_bounds__(kKnnThreads) __attribute__((amdgpu_waves_per_eu(8, 
 // waves per SIMD even at the cost of a small spill; the lags a group repeats are cheap next
 // to that.
 // ---------------------------------------------------------------------------------------
+// 8-wave workgroups; 16-wave ones for long series, where a workgroup's LDS (the series, the
+// bitmaps) would otherwise let fewer than kSimplexOcc waves per SIMD share a CU
 constexpr int kSimplexThreads = 512;
+constexpr int kSimplexMaxThreads = 1024;
 constexpr int kSimplexOcc = 8;
 // (group, first E, last E); every group holds an even number of lists
 #define CCM_SIMPLEX_GROUPS(X) X(0, 1, 4) X(1, 5, 8) X(2, 9, 12) X(3, 13, 16) X(4, 17, 20)
@@ -481,7 +484,7 @@ __device__ __forceinline__ void seed_group(const float* x, int t, int tau, int c
 template <int ELO, int EHI, bool TAU1>
 __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, int E_max, int tau,
                                               int Tp, bool half, int wave, int nw, uint32_t* bm,
-                                              double (&wsum)[kSimplexThreads / kWave][kGroupE][5]) {
+                                              double (&wsum)[kSimplexMaxThreads / kWave][kGroupE][5]) {
   constexpr int NG = EHI - ELO + 1;
   const int lane = lane_id();
   const int E_lo = ELO > E_min ? ELO : E_min;
@@ -595,13 +598,13 @@ __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, 
   }
 }
 
-__global__ __launch_bounds__(kSimplexThreads) __attribute__((amdgpu_waves_per_eu(kSimplexOcc, kSimplexOcc))) void simplex_kernel(
+__global__ __launch_bounds__(kSimplexMaxThreads) __attribute__((amdgpu_waves_per_eu(kSimplexOcc, kSimplexOcc))) void simplex_kernel(
     const float* __restrict__ ts, int64_t ld, int L, const int* __restrict__ ids, int E_min,
     int E_max, int tau, int Tp, int mode, double* __restrict__ rho64) {
   // dynamic LDS: the series after kPad zeros, then each wave's bitmap over times (W words)
   extern __shared__ float xbuf[];
   float* x = xbuf + kPad;
-  __shared__ double wsum[kSimplexThreads / kWave][kGroupE][5];
+  __shared__ double wsum[kSimplexMaxThreads / kWave][kGroupE][5];
   const int grp = kNGroups - 1 - (int)blockIdx.y;   // the groups of larger E (longer) first
   const int series = blockIdx.x;
   const int ELO = group_lo(grp);
@@ -723,10 +726,18 @@ extern "C" hipError_t ccm_launch_simplex(const float* ts, int64_t ld, int L, con
   static std::atomic<uint64_t> attr{0};
   hipError_t e = ccm::allow_lds_once((const void*)ccm::simplex_kernel, attr);
   if (e != hipSuccess) return e;
-  const size_t lds = (size_t)(L + ccm::kPad) * sizeof(float) +
-                     (size_t)(ccm::kSimplexThreads / ccm::kWave) * ((L + 31) / 32) * sizeof(uint32_t);
-  hipLaunchKernelGGL(ccm::simplex_kernel, dim3(n, ccm::kNGroups), dim3(ccm::kSimplexThreads), lds, stream, ts,
-                     ld, L, ids, E_min, E_max, tau, Tp, mode, rho64);
+  // dynamic LDS: the series, then each wave's bitmap over times
+  auto lds_for = [&](int threads) {
+    return (size_t)(L + ccm::kPad) * sizeof(float) +
+           (size_t)(threads / ccm::kWave) * ((L + 31) / 32) * sizeof(uint32_t);
+  };
+  // 8-wave workgroups while four of them (kSimplexOcc waves per SIMD) fit a CU's LDS with the
+  // static part (under 11 KB), else 16-wave ones
+  const int threads =
+      4 * (lds_for(ccm::kSimplexThreads) + 11 * 1024) <= 160 * 1024 ? ccm::kSimplexThreads
+                                                                   : ccm::kSimplexMaxThreads;
+  hipLaunchKernelGGL(ccm::simplex_kernel, dim3(n, ccm::kNGroups), dim3(threads), lds_for(threads),
+                     stream, ts, ld, L, ids, E_min, E_max, tau, Tp, mode, rho64);
   hipLaunchKernelGGL(ccm::simplex_finalize_kernel, dim3((n + 255) / 256), dim3(256), 0, stream,
                      rho64, n, E_min, E_max, optE, rho_E);
   return hipGetLastError();

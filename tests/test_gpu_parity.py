@@ -210,6 +210,21 @@ def test_longer_horizons(ccm):
     _check_optE(optE.cpu().numpy(), rho.cpu().numpy(), oE, oR, "Tp=2 HALF tau=2")
 
 
+def test_optE_lags_and_clipped_E_ranges(ccm):
+    # tau > 1 with E ranges that start and end inside the kernel's E groups: lists seeded
+    # from neighbouring E must respect each E's own first admissible candidate (E - 1) tau,
+    # and lists of clipped-off E must neither be scored nor feed their neighbours' seeds
+    w = synth.make("logistic64")
+    ts = w.panel
+    ids = np.arange(6)
+    for E_min, E_max, tau in ((3, 17, 2), (5, 14, 3), (2, 2, 2), (19, 20, 1)):
+        _say(f"simplex LOO E={E_min}..{E_max} tau={tau}, logistic64 sample")
+        optE, rho = ccm.simplex_optE(_cuda(ts), ids, E_min, E_max, tau, 1, ccm.MODE_LOO)
+        oE, oR, _ = O.simplex_optE(ts, ids, E_min, E_max, tau, 1)
+        _check_optE(optE.cpu().numpy(), rho.cpu().numpy(), oE, oR,
+                    f"LOO E={E_min}..{E_max} tau={tau}")
+
+
 def test_optE_ratenet_sample_and_half_mode(ccm):
     w = synth.make("ratenet1024")
     ts = w.panel
