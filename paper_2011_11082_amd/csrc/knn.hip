@@ -108,6 +108,23 @@ __device__ __forceinline__ void lag_values(const float* x, int sc, int tau, floa
   }
 }
 
+// Lag values x[sc - e tau] for e = A..NL-1 only (the addressing of lag_values<NL>).
+template <int A, int NL, bool TAU1>
+__device__ __forceinline__ void lag_range(const float* x, int sc, int tau, float (&xs)[NL]) {
+  if constexpr (TAU1) {
+    const char* lds0 = (const char*)(x - kPad);
+    const uint32_t a = (uint32_t)(sc + kPad - (NL - 1)) * 4u;
+#pragma unroll
+    for (int e = A; e < NL; ++e) xs[e] = *(const float*)(lds0 + a + 4u * (NL - 1 - e));
+  } else {
+#pragma unroll
+    for (int e = A; e < NL; ++e) {
+      const int xi = sc - e * tau;
+      xs[e] = x[xi > 0 ? xi : 0];
+    }
+  }
+}
+
 // Build a sorted list from the distinct candidate keys in lanes 0..k1 (~0 where empty): an
 // empty entry becomes ~0 - lane, so all k1 + 1 keys differ and stay above every real key
 // (their index reads negative); a key's rank among them is its lane in the list, and a
@@ -525,6 +542,10 @@ __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, 
       const int E = ELO + g;
       tf[g] = (E >= E_lo && E <= E_hi && t >= qbase + (E - 1) * tau) ? thr_float(thr[g]) : -1.0f;
     }
+    // the largest bound of the group at the start of the scan (bounds only fall during it)
+    float tfmax = tf[0];
+#pragma unroll
+    for (int g = 1; g < NG; ++g) tfmax = fmaxf(tfmax, tf[g]);
     // the window of candidates around t first when some list starts empty (HALF mode:
     // candidates are in the other half, so the window clamps to its end), then every chunk
     // in order.  Candidates that are never admissible start at d^2 = +inf; a list takes the
@@ -538,20 +559,30 @@ __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, 
       const bool inr = s <= chi && (pass < 0 || s < wb || s >= wb + kWave);
       const bool okc = inr && (half || s != t);
       const int sc = s <= chi ? s : chi;
+      // lags 0..CHK-1 first; when no candidate of the chunk is still within the group's
+      // largest bound (d^2 only grows with the lags), the chunk ends there
+      constexpr int CHK = ELO >= 9 ? ELO - 4 : 0;
       float xs[EHI];
-      lag_values<EHI, TAU1>(x, sc, tau, xs);
+      lag_range<0, EHI, TAU1>(x, sc, tau, xs);
       float acc = okc ? 0.0f : INFINITY;
 #pragma unroll
-      for (int e = 0; e < EHI; ++e) {
+      for (int e = 0; e < CHK; ++e) {
         const float df = xq[e] - xs[e];
         acc = acc + df * df;
-        if (e + 1 >= ELO) {
-          const int g = (e + 1 - ELO) >= 0 ? (e + 1 - ELO) : 0;
-          if (ballot(acc <= tf[g]) != 0) {
-            const int E = e + 1;
-            const bool adm = okc && sc >= (E - 1) * tau;
-            offer_chunk(adm ? nkey(acc, s) : ~0ull, key[g], thr[g], E);
-            tf[g] = thr_float(thr[g]);
+      }
+      if (CHK == 0 || ballot(acc <= tfmax) != 0) {
+#pragma unroll
+        for (int e = CHK; e < EHI; ++e) {
+          const float df = xq[e] - xs[e];
+          acc = acc + df * df;
+          if (e + 1 >= ELO) {
+            const int g = (e + 1 - ELO) >= 0 ? (e + 1 - ELO) : 0;
+            if (ballot(acc <= tf[g]) != 0) {
+              const int E = e + 1;
+              const bool adm = okc && sc >= (E - 1) * tau;
+              offer_chunk(adm ? nkey(acc, s) : ~0ull, key[g], thr[g], E);
+              tf[g] = thr_float(thr[g]);
+            }
           }
         }
       }
