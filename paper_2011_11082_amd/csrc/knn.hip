@@ -301,18 +301,28 @@ __device__ __forceinline__ void knn_query(const float* x, const uint8_t* mb, int
     const int s = b + lane;
     const bool inr = s <= hi && (pass < 0 || s < wb || s >= wb + kWave);
     const int sc = s <= hi ? s : hi;
+    // lags 0..CHK-1 first; when no lane is still within the list's bound (d^2 only grows
+    // with the lags), the chunk ends there
+    constexpr int CHK = E >= 9 ? E - 4 : 0;
     float xs[E];
     lag_values<E, TAU1>(x, sc, tau, xs);
     float acc = 0.0f;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
+    for (int e = 0; e < CHK; ++e) {
       const float df = xq[e] - xs[e];
       acc = acc + df * df;
     }
-    bool adm = inr && s != t;
-    if (mb) adm = adm && mb[sc] != 0;   // library subsample: only marked candidates
-    const uint64_t cand = adm ? nkey(acc, s) : ~0ull;
-    offer_chunk(cand, key, thr, E);
+    if (CHK == 0 || ballot(acc <= thr_float(thr)) != 0) {
+#pragma unroll
+      for (int e = CHK; e < E; ++e) {
+        const float df = xq[e] - xs[e];
+        acc = acc + df * df;
+      }
+      bool adm = inr && s != t;
+      if (mb) adm = adm && mb[sc] != 0;   // library subsample: only marked candidates
+      const uint64_t cand = adm ? nkey(acc, s) : ~0ull;
+      offer_chunk(cand, key, thr, E);
+    }
   }
 }
 
