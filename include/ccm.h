@@ -176,9 +176,10 @@ ccm_status ccm_simplex_optE_noalloc(const float* ts, int64_t ld, int32_t L, cons
  *   yhat_ij(t) = sum_k w_i[t,k] * ts[n_ik(t) * ld + j];  rho[i][j - tgt0] = Pearson over
  *   t = (E_i-1) tau .. L-1 of (ts[t * ld + j], yhat_ij(t)); NaN where a variance vanishes.
  *   precision CCM_PRECISION_FP32: FP32 products and sums per prediction, FP64 moments.
- *     Up to L = 2475 each 16-target tile sits in LDS; longer series (to CCM_L_MAX) read a
- *     global copy of the tile through L2, which the workspace then holds (n_tgt x L x 4
- *     bytes plus 5.4 KB per 16 targets).
+ *     The target tile sits in LDS: 16 targets up to L = 2475, 8 up to L = 5035; longer
+ *     series (to CCM_L_MAX) read 32-target tiles from a global copy through L2, which the
+ *     workspace then holds (n_tgt x L x 4 bytes plus 10.8 KB per 32 targets).
+ *     ccm_set_gather_tile can force a tile width for testing.
  *   precision CCM_PRECISION_BF16: target values and weights rounded to BF16, contracted on
  *   MFMA with FP32 accumulation; observed values FP32; FP64 moments.
  *   Both forms first centre each target column on c_j, its mean over t = 0..L-1 rounded to
@@ -211,7 +212,7 @@ ccm_status ccm_crossmap_rho(const float* ts, int64_t ld, int32_t L, const int32_
  *   moments; NaN where a variance vanishes.
  *   rho [n_lib][n_tgt], moments [n_lib][n_tgt][3] (nullable) as in ccm_crossmap_rho.
  *   Targets are grouped by E on the device (no host synchronisation).
- *   Series longer than 2475 steps use the global tile copy as in ccm_crossmap_rho.
+ *   Tile widths (LDS or the global copy) follow L as in ccm_crossmap_rho.
  * Errors: EINVAL (nulls, sizes), ERANGE (E_lo, n_E, k_max, L), EWORKSPACE.  Workspace:
  * ccm_workspace_size(CCM_OP_CROSSMAP_TARGET_E, L, n_E * n_lib, n_tgt, k_max).
  */
@@ -272,6 +273,22 @@ ccm_status ccm_workspace_size(int32_t op, int32_t L, int32_t n_lib, int32_t n_tg
  * unspecified (typically NaN) outputs, never a fault.  Always returns CCM_OK.
  */
 ccm_status ccm_set_check_finite(int32_t on);
+
+/*
+ * ccm_set_gather_tile -- testing switch (process-wide) for the FP32 cross-map's target tile
+ * (ccm_crossmap_rho and ccm_crossmap_rho_target_E).
+ *   targets  0 (the default): chosen from L -- 16 targets per tile in LDS while that tile
+ *            fits (L <= 2475), then 8 (L <= 5035), beyond that 32 targets read from a
+ *            global copy of the tile kept in the workspace;
+ *            4, 8 or 16: that LDS tile wherever it fits (4 targets: L <= 10155), else the
+ *            default choice;
+ *            32: the global copy at every L.
+ * Every tile width computes the same products; only the order of a row's FP32 products can
+ * differ, so rho agrees within FP32 rounding.  Workspace sizes follow the switch: set it
+ * before ccm_workspace_size and keep it until the call has been enqueued.
+ * Errors: EINVAL for any other value.
+ */
+ccm_status ccm_set_gather_tile(int32_t targets);
 
 /* Static text of a status code. */
 const char* ccm_status_string(ccm_status s);

@@ -32,7 +32,8 @@ EXPORTED = (
     "ccm_embed", "ccm_knn", "ccm_knn_subset", "ccm_simplex_optE", "ccm_simplex_optE_noalloc",
     "ccm_crossmap_rho",
     "ccm_crossmap_rho_backward", "ccm_crossmap_rho_target_E", "ccm_workspace_size",
-    "ccm_set_check_finite", "ccm_status_string", "ccm_last_error", "ccm_version",
+    "ccm_set_check_finite", "ccm_set_gather_tile", "ccm_status_string", "ccm_last_error",
+    "ccm_version",
 )
 
 
@@ -77,6 +78,7 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
                                       _I32, _I32, _P, _P, _P, _SZ, _P],
         "ccm_workspace_size": [_I32, _I32, _I32, _I32, _I32, ctypes.POINTER(_SZ)],
         "ccm_set_check_finite": [_I32],
+        "ccm_set_gather_tile": [_I32],
         "ccm_status_string": [_I32],
         "ccm_last_error": [],
         "ccm_version": [],
@@ -137,6 +139,12 @@ def set_check_finite(on: bool) -> None:
     """Debug mode (process-wide): every call first checks that the values it reads are
     finite, synchronising its stream, and raises CCMError (CCM_EINVAL) if one is not."""
     _check(load_library().ccm_set_check_finite(1 if on else 0))
+
+
+def set_gather_tile(targets: int) -> None:
+    """Testing switch (process-wide) for the FP32 cross-map's target tile: 0 chooses it from
+    L; 4, 8 or 16 force that LDS tile where it fits; 32 forces the global tile copy."""
+    _check(load_library().ccm_set_gather_tile(int(targets)))
 
 
 def workspace_size(op: int, L: int, n_lib: int, n_tgt: int, k_max: int) -> int:

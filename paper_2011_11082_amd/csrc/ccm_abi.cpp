@@ -23,6 +23,7 @@ hipError_t ccm_launch_embed(const float* ts, int64_t ld, int L, const int* ids, 
 size_t ccm_gather_lds_bytes(int L);
 int ccm_gather_tile_in_lds(int L);
 int ccm_gather_tile_targets(int L);
+void ccm_gather_force_tile(int tj);
 hipError_t ccm_launch_crossmap_fp32(const float* ts, int64_t ld, int L, int tau, int tgt0,
                                     int n_tgt, const int* nbr_idx, const float* nbr_w,
                                     const int* lib_E, int n_lib, int k_max, float* rho,
@@ -77,11 +78,15 @@ struct CrossmapWs {
 CrossmapWs crossmap_ws(int L, int n_lib, int k_max, int n_tiles, int tj) {
   CrossmapWs w;
   const size_t KSM = (size_t)(k_max + 3) / 4;
-  // tables blocked by 16 query rows (16-target tile) or 8 (32-target tile), with spare
-  // blocks after the last library: the gather prefetches block b + 1 unguarded
-  const size_t ent16 = ((size_t)n_lib * ((L + 15) / 16) + 3) * KSM * 64;
-  const size_t ent32 = ((size_t)n_lib * ((L + 7) / 8) + 3) * KSM * 32;
-  const size_t ent = ent16 > ent32 ? ent16 : ent32;
+  // tables blocked by RB = 64 / (tj / 4) query rows (4 entries per row and slot), with spare
+  // blocks after the last library: the gather prefetches block b + 1 unguarded; sized for
+  // every tile width
+  size_t ent = 0;
+  for (int w = 4; w <= 32; w *= 2) {
+    const size_t rb = 64 / (size_t)(w / 4);
+    const size_t e = ((size_t)n_lib * ((L + rb - 1) / rb) + 3) * KSM * 4 * rb;
+    if (e > ent) ent = e;
+  }
   w.off_poff = 0;
   w.off_pw = align_up(w.off_poff + ent * 4);
   w.off_libk = align_up(w.off_pw + ent * 4);
@@ -93,7 +98,8 @@ CrossmapWs crossmap_ws(int L, int n_lib, int k_max, int n_tiles, int tj) {
   return w;
 }
 
-// The library-E cross-map: 16-target tiles in LDS, or 32-target tiles from the global copy.
+// The library-E cross-map: 16-, 8- or 4-target tiles in LDS, or 32-target tiles from the
+// global copy.
 CrossmapWs fp32_ws(int L, int n_lib, int k_max, int n_tgt) {
   const int tj = ccm_gather_tile_targets(L);
   return crossmap_ws(L, n_lib, k_max, (n_tgt + tj - 1) / tj, tj);
@@ -229,6 +235,13 @@ const char* ccm_version(void) { return "ccm-gfx950 0.1"; }
 
 ccm_status ccm_set_check_finite(int32_t on) {
   g_check_finite.store(on ? 1 : 0, std::memory_order_relaxed);
+  return CCM_OK;
+}
+
+ccm_status ccm_set_gather_tile(int32_t targets) {
+  if (targets != 0 && targets != 4 && targets != 8 && targets != 16 && targets != 32)
+    return fail(CCM_EINVAL, "ccm_set_gather_tile", "targets must be 0, 4, 8, 16 or 32");
+  ccm_gather_force_tile(targets);
   return CCM_OK;
 }
 

@@ -29,8 +29,9 @@
 //     column sums.  rho is formed in FP64.
 //   * Waves of every workgroup visit libraries in the same order (heaviest first), so the
 //     32 workgroups of one XCD read the same tables at about the same time and share L2.
-//   * Series longer than the LDS tile holds (L > 2475) read a global copy of the tile
-//     through L2 instead, with the same tables and arithmetic (see gather_fp32_kernel<true>).
+//   * Series longer than the 16-target tile holds (L > 2475) use 8-target tiles in LDS up
+//     to L = 5035, beyond that a global copy of 32-target tiles read through L2, with the
+//     same tables and arithmetic (see gather_fp32_kernel<true>).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -43,17 +44,19 @@ namespace ccm {
 
 constexpr int kTJ = 16;                 // targets per tile in LDS
 constexpr int kGatherThreads = 1024;    // 16 waves
-constexpr int kRowBytes = kTJ * 4;
 
 // Tile geometry for TJ targets per tile: LPR = TJ / 4 lanes per query row (each reads 16
 // bytes of a neighbour row), RB = 64 / LPR query rows per wave block, SLOT = 4 RB table
 // entries per slot of four steps, ROW bytes per time step of the tile.
+// BANK rows of the tile share one 256-byte line of LDS banks (at least 4: the bank rule of
+// the table preparation uses 4 groups for the 32-target global tile too).
 template <int TJ>
 struct Geo {
   static constexpr int LPR = TJ / 4;
   static constexpr int RB = kWave / LPR;
   static constexpr int SLOT = RB * 4;
   static constexpr int ROW = TJ * 4;
+  static constexpr int BANK = 64 / TJ < 4 ? 4 : 64 / TJ;
 };
 
 // ---------------------------------------------------------------------------------------
@@ -86,7 +89,7 @@ __global__ __launch_bounds__(256) void order_kernel(const int* __restrict__ lib_
 // Table preparation: per (library, t) row, reorder the k entries for bank quarters and
 // write them blocked as [lib][t/RB][slot][G][l] (entry j = 4*slot + l of query t = RB b + G,
 // RB = 16 for the 16-target tile, 8 for the 32-target one) as tile byte offsets + weights.
-// Padding entries point at row (t+j) mod 4 with weight 0.
+// Padding entries point at row (t+j) mod BANK with weight 0.
 // ---------------------------------------------------------------------------------------
 template <int TJ>
 __global__ __launch_bounds__(256) void prep_tables_kernel(
@@ -122,10 +125,10 @@ __global__ __launch_bounds__(256) void prep_tables_kernel(
     }
     uint32_t used = 0;
     for (int j = 0; j < k; ++j) {
-      const int c = (t + j) & 3;
+      const int c = (t + j) & (Gm::BANK - 1);
       int pick = -1;
       for (int m = 0; m < k; ++m)
-        if (!((used >> m) & 1) && idx[m] >= 0 && (idx[m] & 3) == c) {
+        if (!((used >> m) & 1) && idx[m] >= 0 && (idx[m] & (Gm::BANK - 1)) == c) {
           pick = m;
           break;
         }
@@ -143,7 +146,7 @@ __global__ __launch_bounds__(256) void prep_tables_kernel(
   const int G = t % Gm::RB;
   for (int j = 0; j < KSM * 4; ++j) {
     const size_t pos = (((size_t)i * nblk + b) * KSM + (j >> 2)) * Gm::SLOT + G * 4 + (j & 3);
-    uint32_t o = (uint32_t)(((t + j) & 3) * Gm::ROW);
+    uint32_t o = (uint32_t)(((t + j) & (Gm::BANK - 1)) * Gm::ROW);
     float wv = 0.0f;
     if (j < nsel) {
       int m = sel[j];
@@ -266,46 +269,83 @@ __device__ __forceinline__ void fold(Moments& m) {
   m.sp = m.spp = m.syp = float4{0, 0, 0, 0};
 }
 
-// Table entries of one block held by one lane: slot s covers steps 4s..4s+3.  Lane 4G + l
-// holds the LDS offset of step 4s + l of query G (broadcast inside the quad when the read
-// address is formed) and all four weights of the slot (one 16-byte load from an address the
-// quad shares, so the memory system fetches each weight once).
-template <int KS>
+// Table entries of one block held by one lane: slot s covers steps 4s..4s+3.  With four or
+// more lanes per query row (16- and 32-target tiles), lane 4G + l holds the LDS offset of
+// step 4s + l of query G (broadcast inside the quad when the read address is formed); with
+// two (8 targets) each lane holds two steps' offsets, broadcast inside its pair; with one
+// (4 targets) a lane holds all four and needs no broadcast.  Every lane holds all four
+// weights of the slot (one 16-byte load from an address the query's lanes share, so the
+// memory system fetches each weight once).
+template <int TJ>
+struct SlotOff {
+  using type = uint32_t;
+};
+template <>
+struct SlotOff<8> {
+  using type = uint2;
+};
+template <>
+struct SlotOff<4> {
+  using type = uint4;
+};
+
+template <int KS, int TJ>
 struct Slots {
-  uint32_t off[KS];
+  typename SlotOff<TJ>::type off[KS];
   float4 wgt[KS];
 };
 
 template <int S, int TJ, int KS>
 __device__ __forceinline__ void load_slot(const uint32_t* bo, const float* bw, int lane,
-                                          Slots<KS>& e) {
+                                          Slots<KS, TJ>& e) {
   using Gm = Geo<TJ>;
   const int q = (lane / Gm::LPR) * 4;   // first entry of this lane's query row
-  e.off[S] = bo[S * Gm::SLOT + q + (lane & 3)];
+  if constexpr (Gm::LPR >= 4) e.off[S] = bo[S * Gm::SLOT + q + (lane & 3)];
+  else if constexpr (Gm::LPR == 2) e.off[S] = *(const uint2*)(bo + S * Gm::SLOT + q + 2 * (lane & 1));
+  else e.off[S] = *(const uint4*)(bo + S * Gm::SLOT + q);
   e.wgt[S] = *(const float4*)(bw + S * Gm::SLOT + q);
 }
 
-template <int J, int K>
-__device__ __forceinline__ void pair_reads(const char* tile, const Slots<(K + 3) / 4>& e,
+// LDS offset of step M (0..3) of a slot for this lane's query row.
+template <int M, int TJ>
+__device__ __forceinline__ uint32_t step_off(const typename SlotOff<TJ>::type& o) {
+  if constexpr (Geo<TJ>::LPR >= 4) {
+    return (uint32_t)quad_bcast<M>((int)o);
+  } else if constexpr (Geo<TJ>::LPR == 2) {
+    // lanes 4q + {0, 1} (one row) take lane 4q + M / 2, lanes 4q + {2, 3} lane 4q + 2 + M / 2
+    constexpr int a = M >> 1;
+    constexpr int sel = a | (a << 2) | ((2 + a) << 4) | ((2 + a) << 6);
+    const int v = (M & 1) ? (int)o.y : (int)o.x;
+    return (uint32_t)__builtin_amdgcn_mov_dpp(v, sel, 0xF, 0xF, true);
+  } else {
+    if constexpr (M == 0) return o.x;
+    else if constexpr (M == 1) return o.y;
+    else if constexpr (M == 2) return o.z;
+    else return o.w;
+  }
+}
+
+template <int J, int K, int TJ>
+__device__ __forceinline__ void pair_reads(const char* tile, const Slots<(K + 3) / 4, TJ>& e,
                                            uint32_t laneoff, float4 (&y)[2]) {
   constexpr int S = J >> 2;
   if (J + 0 < K)
-    y[0] = *(const float4*)(tile + (uint32_t)quad_bcast<(J & 3)>((int)e.off[S]) + laneoff);
+    y[0] = *(const float4*)(tile + step_off<(J & 3), TJ>(e.off[S]) + laneoff);
   if (J + 1 < K)
-    y[1] = *(const float4*)(tile + (uint32_t)quad_bcast<((J + 1) & 3)>((int)e.off[S]) + laneoff);
+    y[1] = *(const float4*)(tile + step_off<((J + 1) & 3), TJ>(e.off[S]) + laneoff);
 }
 
 // One table row, software-pipelined by pairs of steps (reads of pair p+1 issued before the
 // products of pair p).  Once the products of a slot are done its registers are reloaded
 // with the same slot of the next block, a whole block ahead of use.
 template <int K, int TJ, int J = 0>
-__device__ __forceinline__ void gather_row_pipe(const char* tile, Slots<(K + 3) / 4>& e,
+__device__ __forceinline__ void gather_row_pipe(const char* tile, Slots<(K + 3) / 4, TJ>& e,
                                                 const uint32_t* nbo, const float* nbw, int lane,
                                                 uint32_t laneoff, float4 (&ya)[2],
                                                 float4 (&yb)[2], float4& acc) {
   if constexpr (J < K) {
     constexpr int S = J >> 2;
-    if constexpr (J + 2 < K) pair_reads<J + 2, K>(tile, e, laneoff, yb);
+    if constexpr (J + 2 < K) pair_reads<J + 2, K, TJ>(tile, e, laneoff, yb);
     fma4<J == 0>(acc, wcomp<(J & 3)>(e.wgt[S]), ya[0]);
     if constexpr (J + 1 < K) fma4<false>(acc, wcomp<((J + 1) & 3)>(e.wgt[S]), ya[1]);
     if constexpr ((J + 2) % 4 == 0 || J + 2 >= K) load_slot<S, TJ>(nbo, nbw, lane, e);
@@ -314,14 +354,14 @@ __device__ __forceinline__ void gather_row_pipe(const char* tile, Slots<(K + 3) 
 }
 
 template <int K, int TJ>
-__device__ __forceinline__ void gather_block(const char* smem, Slots<(K + 3) / 4>& e,
+__device__ __forceinline__ void gather_block(const char* smem, Slots<(K + 3) / 4, TJ>& e,
                                              const uint32_t* nbo, const float* nbw, int lane,
                                              uint32_t laneoff, int t, int L, Moments& m) {
   float4 acc, ya[2], yb[2];
   // a wave issuing its row's reads and products runs ahead of waves in their moment
   // updates (65.0 -> 61.1 ms on 512 x 101,729 at L = 1600, identical rho)
   __builtin_amdgcn_s_setprio(1);
-  pair_reads<0, K>(smem, e, laneoff, ya);
+  pair_reads<0, K, TJ>(smem, e, laneoff, ya);
   gather_row_pipe<K, TJ>(smem, e, nbo, nbw, lane, laneoff, ya, yb, acc);
   __builtin_amdgcn_s_setprio(0);
   t = t < L ? t : L - 1;
@@ -335,7 +375,7 @@ __device__ __forceinline__ void gather_block(const char* smem, Slots<(K + 3) / 4
 
 template <int K, int TJ, int S = 0>
 __device__ __forceinline__ void load_all(const uint32_t* bo, const float* bw, int lane,
-                                         Slots<(K + 3) / 4>& e) {
+                                         Slots<(K + 3) / 4, TJ>& e) {
   if constexpr (S < (K + 3) / 4) {
     load_slot<S, TJ>(bo, bw, lane, e);
     load_all<K, TJ, S + 1>(bo, bw, lane, e);
@@ -354,7 +394,7 @@ __device__ __forceinline__ void gather_library(const char* smem, const uint32_t*
   const size_t bstride = (size_t)KSM * Geo<TJ>::SLOT;
   const uint32_t* bo = po + (size_t)b0 * bstride;
   const float* bw = pq + (size_t)b0 * bstride;
-  Slots<(K + 3) / 4> e;
+  Slots<(K + 3) / 4, TJ> e;
   load_all<K, TJ>(bo, bw, lane, e);
   int b = b0;
   while (b < nblk) {
@@ -467,7 +507,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
     double* __restrict__ moments, const int* __restrict__ tiles, const int* __restrict__ ntiles,
     const int* __restrict__ perm, int n_E, const float* __restrict__ gtile,
     const double* __restrict__ gsum, int n_tiles, int gsplits) {
-  static_assert(GT || TJ == kTJ, "the LDS tile has 16 columns");
+  static_assert(GT || TJ == 4 || TJ == 8 || TJ == kTJ, "LDS tiles of 4, 8 or 16 columns");
   using Gm = Geo<TJ>;
   extern __shared__ __align__(16) char smem[];
   __shared__ int colmap[TJ];    // target column of each tile column, -1 if none
@@ -503,51 +543,52 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
   };
   auto sums_ptr = [&]() -> const double* {
     if constexpr (GT) return gsum + (size_t)T * 2 * (kEMax + 1) * TJ;
-    else return (const double*)(smem + (size_t)L * kRowBytes);
+    else return (const double*)(smem + (size_t)L * Gm::ROW);
   };
   if constexpr (!GT) {
     float* tile = (float*)smem;
-    double* lsy = (double*)(smem + (size_t)L * kRowBytes);
-    double* lsyy = lsy + (kEMax + 1) * kTJ;
-    // load the tile (rows 0..L-1, 16 columns; missing columns read as 0).  A thread always
-    // handles the same column (blockDim is a multiple of 16), so it sums that column too.
+    double* lsy = (double*)(smem + (size_t)L * Gm::ROW);
+    double* lsyy = lsy + (kEMax + 1) * TJ;
+    // load the tile (rows 0..L-1, TJ columns; missing columns read as 0).  A thread always
+    // handles the same column (blockDim is a multiple of TJ), so it sums that column too.
+    constexpr int SH = TJ == 16 ? 4 : (TJ == 8 ? 3 : 2);   // log2 TJ
     double csum = 0.0;
-    for (int g = threadIdx.x; g < L * kTJ; g += blockDim.x) {
-      const int t = g >> 4;
-      const int j = colmap[g & 15];
+    for (int g = threadIdx.x; g < L * TJ; g += blockDim.x) {
+      const int t = g >> SH;
+      const int j = colmap[g & (TJ - 1)];
       const float v = j >= 0 ? ts[(int64_t)t * ld + tgt0 + j] : 0.0f;
       tile[g] = v;
       csum += v;
     }
     // centre each column on c = its mean rounded to FP32 (kept in the unused E = 0 slot of
-    // the sums, lsy[c]); the per-wave partial sums pass through lsy[16 ..] first
-    csum += __shfl_xor(csum, 16);
-    csum += __shfl_xor(csum, 32);
-    if (lane_id() < kTJ) lsy[kTJ + (threadIdx.x / kWave) * kTJ + lane_id()] = csum;
+    // the sums, lsy[c]); the per-wave partial sums pass through lsy[TJ ..] first
+#pragma unroll
+    for (int o = TJ; o < kWave; o <<= 1) csum += __shfl_xor(csum, o);
+    if (lane_id() < TJ) lsy[TJ + (threadIdx.x / kWave) * TJ + lane_id()] = csum;
     __syncthreads();
-    if (threadIdx.x < kTJ) {
+    if (threadIdx.x < TJ) {
       double tot = 0.0;
-      for (int w = 0; w < kGatherThreads / kWave; ++w) tot += lsy[kTJ + w * kTJ + threadIdx.x];
+      for (int w = 0; w < kGatherThreads / kWave; ++w) tot += lsy[TJ + w * TJ + threadIdx.x];
       lsy[threadIdx.x] = (double)(float)(tot / L);
     }
     __syncthreads();
     {
-      const float cj = (float)lsy[threadIdx.x & 15];
-      for (int g = threadIdx.x; g < L * kTJ; g += blockDim.x) tile[g] -= cj;
+      const float cj = (float)lsy[threadIdx.x & (TJ - 1)];
+      for (int g = threadIdx.x; g < L * TJ; g += blockDim.x) tile[g] -= cj;
     }
     __syncthreads();
     // FP64 sums of y and y^2 over t >= (E-1) tau, per E and column
-    for (int g = threadIdx.x; g < kEMax * kTJ; g += blockDim.x) {
-      const int E = g / kTJ + 1;
-      const int c = g % kTJ;
+    for (int g = threadIdx.x; g < kEMax * TJ; g += blockDim.x) {
+      const int E = g / TJ + 1;
+      const int c = g % TJ;
       double a = 0.0, a2 = 0.0;
       for (int t = (E - 1) * tau; t < L; ++t) {
-        double v = tile[t * kTJ + c];
+        double v = tile[t * TJ + c];
         a += v;
         a2 += v * v;
       }
-      lsy[E * kTJ + c] = a;
-      lsyy[E * kTJ + c] = a2;
+      lsy[E * TJ + c] = a;
+      lsyy[E * TJ + c] = a2;
     }
     __syncthreads();
   }
@@ -629,10 +670,11 @@ __global__ __launch_bounds__(kGatherThreads) void gather_fp32_kernel(
 
 namespace ccm {
 // The gather's LDS tile needs more than the default dynamic LDS limit: allow all of the
-// CU's 160 KB minus the kernel's static LDS.
+// CU's 160 KB minus the kernel's static LDS (once per tile width).
+template <int TJ>
 hipError_t gather_allow_lds() {
   static std::atomic<uint64_t> done{0};
-  return allow_lds_once((const void*)gather_fp32_kernel<false, kTJ>, done);
+  return allow_lds_once((const void*)gather_fp32_kernel<false, TJ>, done);
 }
 
 // Library splits (grid.y): enough workgroups to fill the chip when there are few tiles, no
@@ -652,47 +694,68 @@ int gather_splits_global(int n_lib) {
 
 }  // namespace ccm
 
-extern "C" size_t ccm_gather_lds_bytes(int L);
-
-// 1 when the 16-target tile of L time steps (plus the column sums) fits in LDS.
-extern "C" int ccm_gather_tile_in_lds(int L) {
-  return ccm_gather_lds_bytes(L) + ccm::kTJ * sizeof(int) <= 160 * 1024 ? 1 : 0;
+// LDS of a tile of tj targets over L time steps: the tile plus its FP64 column sums.
+static size_t gather_lds_bytes_tj(int L, int tj) {
+  return (size_t)L * tj * 4 + 2 * (ccm::kEMax + 1) * (size_t)tj * sizeof(double);
+}
+static bool gather_fits_lds(int L, int tj) {
+  return gather_lds_bytes_tj(L, tj) + (size_t)tj * sizeof(int) <= 160 * 1024;
 }
 
-// Targets per tile of the cross-map: 16 in LDS, 32 from the global copy.
+// Testing switch (ccm_set_gather_tile): 0 picks the tile width from L; 4, 8 or 16 force that
+// LDS tile where it fits; 32 forces the global copy.
+static std::atomic<int> g_force_tile{0};
+extern "C" void ccm_gather_force_tile(int tj) {
+  g_force_tile.store(tj == 4 || tj == 8 || tj == 16 || tj == 32 ? tj : 0);
+}
+
+// Targets per tile of the cross-map: 16 while that tile fits in LDS (L <= 2475), then 8
+// (L <= 5,035: each time step's row half as wide, each table read for half as many targets,
+// but the neighbour rows stay on chip), beyond that 32 targets from a global copy.  The
+// 4-target LDS tile (L <= 10,155) is built and can be forced, but at L = 8,528 it measured
+// no faster than the global copy.
 extern "C" int ccm_gather_tile_targets(int L) {
-  return ccm_gather_tile_in_lds(L) ? ccm::kTJ : 2 * ccm::kTJ;
+  const int f = g_force_tile.load();
+  if (f == 32) return 32;
+  if (f != 0 && gather_fits_lds(L, f)) return f;
+  for (int tj = ccm::kTJ; tj >= 8; tj /= 2)
+    if (gather_fits_lds(L, tj)) return tj;
+  return 2 * ccm::kTJ;
 }
+
+// 1 when the cross-map's target tile is in LDS (else a global copy is made).
+extern "C" int ccm_gather_tile_in_lds(int L) { return ccm_gather_tile_targets(L) <= ccm::kTJ; }
 
 namespace ccm {
 // Launch the gather on n_tiles tiles of TJ targets (library-E columns when tiles == NULL,
-// else the tile list), from LDS when the tile fits there (TJ = 16), else from a global copy
-// made first.  The tables were blocked for TJ.
+// else the tile list), from LDS (TJ = 4, 8, 16), else from a global copy made first.  The
+// tables were blocked for TJ.
 template <int TJ>
 hipError_t launch_gather(const float* ts, int64_t ld, int L, int tau, int tgt0, int n_tgt,
                          const uint32_t* poff, const float* pw, const int* order, const int* lib_k,
                          int n_lib, int nblk, int KSM, float* rho, double* moments,
                          const int* tiles, const int* ntiles, const int* perm, int n_E,
                          int n_tiles, float* gtile, double* gsum, hipStream_t stream) {
-  if (TJ == kTJ && ccm_gather_tile_in_lds(L)) {
-    hipError_t e = gather_allow_lds();
+  if constexpr (TJ <= kTJ) {
+    hipError_t e = gather_allow_lds<TJ>();
     if (e != hipSuccess) return e;
     const int splits = gather_splits(n_tiles, n_lib);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(gather_fp32_kernel<false, kTJ>), dim3(n_tiles, splits), dim3(kGatherThreads),
-                       ccm_gather_lds_bytes(L), stream, ts, ld, L, tau, tgt0, n_tgt, poff, pw,
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gather_fp32_kernel<false, TJ>), dim3(n_tiles, splits), dim3(kGatherThreads),
+                       gather_lds_bytes_tj(L, TJ), stream, ts, ld, L, tau, tgt0, n_tgt, poff, pw,
                        order, lib_k, n_lib, nblk, KSM, rho, moments, tiles, ntiles, perm, n_E,
                        (const float*)nullptr, (const double*)nullptr, n_tiles, splits);
     return hipGetLastError();
+  } else {
+    hipLaunchKernelGGL(tile_copy_kernel<TJ>, dim3(n_tiles), dim3(kCopyThreads), 0, stream, ts, ld,
+                       L, tau, tgt0, n_tgt, tiles, ntiles, perm, gtile, gsum);
+    const int splits = gather_splits_global(n_lib);
+    const int64_t grid = (int64_t)((n_tiles + kXcd - 1) / kXcd) * kXcd * splits;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gather_fp32_kernel<true, TJ>), dim3((unsigned)grid), dim3(kGatherThreads), 0,
+                       stream, ts, ld, L, tau, tgt0, n_tgt, poff, pw, order, lib_k, n_lib, nblk, KSM,
+                       rho, moments, tiles, ntiles, perm, n_E, (const float*)gtile,
+                       (const double*)gsum, n_tiles, splits);
+    return hipGetLastError();
   }
-  hipLaunchKernelGGL(tile_copy_kernel<TJ>, dim3(n_tiles), dim3(kCopyThreads), 0, stream, ts, ld, L,
-                     tau, tgt0, n_tgt, tiles, ntiles, perm, gtile, gsum);
-  const int splits = gather_splits_global(n_lib);
-  const int64_t grid = (int64_t)((n_tiles + kXcd - 1) / kXcd) * kXcd * splits;
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(gather_fp32_kernel<true, TJ>), dim3((unsigned)grid), dim3(kGatherThreads), 0,
-                     stream, ts, ld, L, tau, tgt0, n_tgt, poff, pw, order, lib_k, n_lib, nblk, KSM,
-                     rho, moments, tiles, ntiles, perm, n_E, (const float*)gtile,
-                     (const double*)gsum, n_tiles, splits);
-  return hipGetLastError();
 }
 }  // namespace ccm
 
@@ -701,8 +764,9 @@ extern "C" hipError_t ccm_launch_order(const int* lib_k, int n_lib, int* order, 
   return hipGetLastError();
 }
 
-extern "C" size_t ccm_gather_lds_bytes(int L) {  // tile + column sums
-  return (size_t)L * ccm::kRowBytes + 2 * (ccm::kEMax + 1) * ccm::kTJ * sizeof(double);
+extern "C" size_t ccm_gather_lds_bytes(int L) {  // tile + column sums at L's tile width
+  const int tj = ccm_gather_tile_targets(L);
+  return tj <= ccm::kTJ ? gather_lds_bytes_tj(L, tj) : 0;
 }
 
 extern "C" hipError_t ccm_launch_crossmap_fp32(const float* ts, int64_t ld, int L, int tau,
@@ -727,8 +791,12 @@ extern "C" hipError_t ccm_launch_crossmap_fp32(const float* ts, int64_t ld, int 
                                   nblk, KSM, rho, moments, nullptr, nullptr, nullptr, 0, n_tiles,
                                   gtile, gsum, stream);
   };
-  if (ccm_gather_tile_targets(L) == ccm::kTJ) return run(std::integral_constant<int, ccm::kTJ>{});
-  return run(std::integral_constant<int, 2 * ccm::kTJ>{});
+  switch (ccm_gather_tile_targets(L)) {
+    case 16: return run(std::integral_constant<int, 16>{});
+    case 8: return run(std::integral_constant<int, 8>{});
+    case 4: return run(std::integral_constant<int, 4>{});
+    default: return run(std::integral_constant<int, 32>{});
+  }
 }
 
 // Maximum number of tile entries for n_tgt targets in tiles of tj columns: every bucket may
@@ -761,6 +829,10 @@ extern "C" hipError_t ccm_launch_crossmap_fp32_target_E(
                                   nblk, KSM, rho, moments, tiles, ntiles, perm, n_E,
                                   ccm_target_E_max_tiles(n_tgt, TJ), gtile, gsum, stream);
   };
-  if (ccm_gather_tile_targets(L) == ccm::kTJ) return run(std::integral_constant<int, ccm::kTJ>{});
-  return run(std::integral_constant<int, 2 * ccm::kTJ>{});
+  switch (ccm_gather_tile_targets(L)) {
+    case 16: return run(std::integral_constant<int, 16>{});
+    case 8: return run(std::integral_constant<int, 8>{});
+    case 4: return run(std::integral_constant<int, 4>{});
+    default: return run(std::integral_constant<int, 32>{});
+  }
 }

@@ -96,12 +96,28 @@ def test_argument_errors_return_status_before_device_work():
                                 _null(), _null(), 0, _null()) == ccm.CCM_EINVAL
     assert lib.ccm_crossmap_rho(fake, 64, 100, fake, fake, fake, 4, 21, 1, 0, 64, 9, fake, _null(),
                                 _null(), 0, _null()) == ccm.CCM_EINVAL
-    # beyond the LDS tile (L > 2475) the FP32 form keeps a global tile copy in the workspace
     assert lib.ccm_crossmap_rho(fake, 64, 4000, fake, fake, fake, 4, 21, 1, 0, 64, 0, fake,
                                 _null(), _null(), 0, _null()) == ccm.CCM_EWORKSPACE
-    short = ccm.workspace_size(ccm.OP_CROSSMAP_FP32, 2475, 4, 64, 21)
-    long = ccm.workspace_size(ccm.OP_CROSSMAP_FP32, 2476, 4, 64, 21)
-    assert long - short >= 4 * 2476 * 16 * 4 + 4 * 2 * 21 * 16 * 8
+    # the target tile sits in LDS up to L = 5035 (16, then 8 targets); beyond it the FP32
+    # form keeps a global copy of every 32-target tile in the workspace
+    short = ccm.workspace_size(ccm.OP_CROSSMAP_FP32, 5035, 4, 64, 21)
+    long = ccm.workspace_size(ccm.OP_CROSSMAP_FP32, 5036, 4, 64, 21)
+    assert long - short >= 2 * 5036 * 32 * 4 + 2 * 2 * 21 * 32 * 8
+    # the testing switch: a forced global copy shows in the workspace (none at L = 2476 or
+    # 1600 otherwise, nor with a forced LDS width); bad values are refused
+    try:
+        for L in (1600, 2476):
+            auto = ccm.workspace_size(ccm.OP_CROSSMAP_FP32, L, 4, 64, 21)
+            ccm.set_gather_tile(32)
+            forced = ccm.workspace_size(ccm.OP_CROSSMAP_FP32, L, 4, 64, 21)
+            ccm.set_gather_tile(8)
+            assert ccm.workspace_size(ccm.OP_CROSSMAP_FP32, L, 4, 64, 21) == auto
+            ccm.set_gather_tile(0)
+            assert forced - auto >= 2 * L * 32 * 4 + 2 * 2 * 21 * 32 * 8
+    finally:
+        ccm.set_gather_tile(0)
+    assert lib.ccm_set_gather_tile(12) == ccm.CCM_EINVAL
+    assert lib.ccm_set_gather_tile(0) == ccm.CCM_OK
 
 
 def test_backward_argument_errors():

@@ -1,7 +1,9 @@
 """Edge cases of the HIP path against the oracle, through the C ABI: the delay embedding
 (bit-exact, every E and several lags), lag tau = 2 in the cross-map (both precisions), the
-largest series the FP32 LDS tile holds (L = 2475), series beyond it (L = 3000: the tile is
-read from a global copy, in both the library-E and the per-target-E forms), long series in
+largest series the 16-target FP32 LDS tile holds (L = 2475) and series beyond it (L = 3000:
+8-target LDS tiles; L = 6000: the 32-target global copy), each also through every other tile
+width the testing switch can force (the 4-target LDS tile included), in both the library-E and
+the per-target-E forms; long series in
 the table and optE kernels (sampled query rows), the largest length the ABI accepts in the
 tables, both cross-map forms and the adjoint, and empty inputs."""
 import sys
@@ -91,37 +93,75 @@ def test_crossmap_at_the_largest_fp32_tile(ccm):
     lib_ids, lib_E = [0, 7, 33], np.array([2, 5, 9], dtype=np.int32)
     _say("crossmap L=2475, 3 libraries x 40 targets")
     idx, wt, _ = ccm.knn(_cuda(ts), lib_ids, lib_E, k_max=10)
-    rho = ccm.crossmap_rho(_cuda(ts), idx, wt, lib_E).cpu().numpy()
     rho_o, idx_o, _, _ = O.ccm_block(ts, lib_ids, lib_E, 1, 0, 40, k_max=10)
     assert np.array_equal(idx.cpu().numpy(), idx_o)
-    _check_rho(rho, rho_o, "L=2475", 1e-5)
+    try:
+        for tj in (0, 8, 4, 32):             # 0: the 16-target LDS tile
+            _say(f"crossmap L=2475, tile {tj or 16}")
+            ccm.set_gather_tile(tj)
+            rho = ccm.crossmap_rho(_cuda(ts), idx, wt, lib_E).cpu().numpy()
+            _check_rho(rho, rho_o, f"L=2475 tile {tj or 16}", 1e-5)
+    finally:
+        ccm.set_gather_tile(0)
 
 
 def test_crossmap_beyond_the_lds_tile(ccm):
-    L = 3000                                  # past 2475: the tile is read through L2
+    L = 3000                                  # past 2475: 8-target tiles in LDS
     rng = np.random.default_rng(47)
     ts = np.cumsum(rng.standard_normal((L, 40)), axis=0).astype(np.float32)
     ts = ((ts - ts.mean(0)) / ts.std(0)).astype(np.float32)
     lib_ids, lib_E = [0, 7, 33], np.array([2, 7, 20], dtype=np.int32)
     tgt0, n_tgt = 3, 37                       # three tiles, the last one ragged
-    _say("crossmap L=3000 (global tile), 3 libraries x 37 targets")
+    _say("crossmap L=3000, 3 libraries x 37 targets")
     idx, wt, _ = ccm.knn(_cuda(ts), lib_ids, lib_E, k_max=21)
-    rho, mom = ccm.crossmap_rho(_cuda(ts), idx, wt, lib_E, tgt0=tgt0, n_tgt=n_tgt,
-                                want_moments=True)
     rho_o, idx_o, _, _ = O.ccm_block(ts, lib_ids, lib_E, 1, tgt0, n_tgt, k_max=21)
     assert np.array_equal(idx.cpu().numpy(), idx_o)
-    _check_rho(rho.cpu().numpy(), rho_o, "L=3000", 1e-5)
-    assert np.all(np.isfinite(mom.cpu().numpy()))
+    try:
+        for tj in (0, 4, 32):                # 0: the 8-target LDS tile
+            _say(f"crossmap L=3000, tile {tj or 8}")
+            ccm.set_gather_tile(tj)
+            rho, mom = ccm.crossmap_rho(_cuda(ts), idx, wt, lib_E, tgt0=tgt0, n_tgt=n_tgt,
+                                        want_moments=True)
+            _check_rho(rho.cpu().numpy(), rho_o, f"L=3000 tile {tj or 8}", 1e-5)
+            assert np.all(np.isfinite(mom.cpu().numpy()))
+    finally:
+        ccm.set_gather_tile(0)
     r16 = ccm.crossmap_rho(_cuda(ts), idx, wt, lib_E, tgt0=tgt0, n_tgt=n_tgt,
                            precision=ccm.PRECISION_BF16)
     _check_rho(r16.cpu().numpy(), rho_o, "L=3000 BF16", 5e-3)
-    _say("crossmap per-target E, L=3000 (global tile), 2 libraries x 37 targets")
     tgt_E = rng.integers(3, 5, size=n_tgt).astype(np.int32)
     idx, wt, _ = ccm.knn_all_E(_cuda(ts), lib_ids[:2], 3, 2, k_max=21)
-    rho = ccm.crossmap_rho_target_E(_cuda(ts), idx, wt, 2, tgt_E, E_lo=3, tgt0=tgt0,
-                                    n_tgt=n_tgt).cpu().numpy()
     rho_o = O.crossmap_rho_target_E(ts, lib_ids[:2], tgt_E, 1, tgt0, n_tgt, k_max=21)
-    _check_rho(rho, rho_o, "L=3000 per-target E", 1e-5)
+    try:
+        for tj in (0, 32):                   # 0: the 8-target LDS tile
+            _say(f"crossmap per-target E, L=3000, tile {tj or 8}, 2 libraries x 37 targets")
+            ccm.set_gather_tile(tj)
+            rho = ccm.crossmap_rho_target_E(_cuda(ts), idx, wt, 2, tgt_E, E_lo=3, tgt0=tgt0,
+                                            n_tgt=n_tgt).cpu().numpy()
+            _check_rho(rho, rho_o, f"L=3000 per-target E tile {tj or 8}", 1e-5)
+    finally:
+        ccm.set_gather_tile(0)
+
+
+def test_crossmap_global_and_four_target_tiles(ccm):
+    L = 6000                                  # past 5035: the global copy, or 4-target tiles
+    rng = np.random.default_rng(53)
+    ts = np.cumsum(rng.standard_normal((L, 24)), axis=0).astype(np.float32)
+    ts = ((ts - ts.mean(0)) / ts.std(0)).astype(np.float32)
+    lib_ids, lib_E = [0, 11], np.array([3, 12], dtype=np.int32)
+    tgt0, n_tgt = 2, 21                       # six tiles, the last one ragged
+    _say("crossmap L=6000, 2 libraries x 21 targets")
+    idx, wt, _ = ccm.knn(_cuda(ts), lib_ids, lib_E, k_max=13)
+    rho_o, idx_o, _, _ = O.ccm_block(ts, lib_ids, lib_E, 1, tgt0, n_tgt, k_max=13)
+    assert np.array_equal(idx.cpu().numpy(), idx_o)
+    try:
+        for tj in (0, 4):                    # 0: the 32-target global copy
+            _say(f"crossmap L=6000, tile {tj or 32}")
+            ccm.set_gather_tile(tj)
+            rho = ccm.crossmap_rho(_cuda(ts), idx, wt, lib_E, tgt0=tgt0, n_tgt=n_tgt)
+            _check_rho(rho.cpu().numpy(), rho_o, f"L=6000 tile {tj or 32}", 1e-5)
+    finally:
+        ccm.set_gather_tile(0)
 
 
 def test_long_series_tables_and_optE(ccm):

@@ -110,19 +110,25 @@ def test_target_shift_per_target_E_and_long_series(ccm):
     rho_o = O.crossmap_rho_target_E(panel, lib_cols, tgt_E, 1, 0, n_tgt, k_max=21)
     _check_rho(rho, rho_o, "per-target E, 3 y - 1000", RHO_TOL)
 
-    # series longer than the LDS tile: the global tile copy is centred the same way
+    # series longer than the 16-target LDS tile: the 8-target LDS tile and the global tile
+    # copy are centred the same way
     L = 3000
     x = np.cumsum(rng.standard_normal((L, 40)), axis=0)
     x = ((x - x.mean(0)) / x.std(0)).astype(np.float32)
     lib_ids, lib_E = [0, 7, 33], np.array([2, 7, 20], dtype=np.int32)
     Xb = _affine(x, 40, -2.5, 1000.0)
-    _say("invariance: L = 3000 (global tile), targets -2.5 y + 1000")
+    _say("invariance: L = 3000 (8-target and global tiles), targets -2.5 y + 1000")
     idx, wt, _ = ccm.knn(_cuda(x), lib_ids, lib_E, k_max=21)
     idx_o, w_o, _ = O.knn(x, lib_ids, lib_E, 1, 0, 21)
     assert np.array_equal(idx.cpu().numpy(), idx_o)
     rho_o = O.crossmap_rho(Xb, idx_o, w_o, lib_E, 1, 3, 37)
-    rho = ccm.crossmap_rho(_cuda(Xb), idx, wt, lib_E, tgt0=3, n_tgt=37).cpu().numpy()
-    _check_rho(rho, rho_o, "L=3000 FP32, -2.5 y + 1000", RHO_TOL)
+    try:
+        for tj in (0, 32):
+            ccm.set_gather_tile(tj)
+            rho = ccm.crossmap_rho(_cuda(Xb), idx, wt, lib_E, tgt0=3, n_tgt=37).cpu().numpy()
+            _check_rho(rho, rho_o, f"L=3000 FP32 tile {tj or 8}, -2.5 y + 1000", RHO_TOL)
+    finally:
+        ccm.set_gather_tile(0)
     r16 = ccm.crossmap_rho(_cuda(Xb), idx, wt, lib_E, tgt0=3, n_tgt=37,
                            precision=ccm.PRECISION_BF16).cpu().numpy()
     _check_rho(r16, rho_o, "L=3000 BF16, -2.5 y + 1000", BF16_TOL)
