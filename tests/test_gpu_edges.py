@@ -83,6 +83,16 @@ def test_crossmap_tau2_both_precisions(ccm):
     r16 = ccm.crossmap_rho(_cuda(ts), idx, wt, lib_E, tau=2, tgt0=tgt0, n_tgt=n_tgt,
                            precision=ccm.PRECISION_BF16)
     _check_rho(r16.cpu().numpy(), rho_o, "tau=2 BF16", 5e-3)
+    # the narrower tiles and the global copy at tau = 2 (the tables' first rows and the
+    # column sums start at (E - 1) tau)
+    try:
+        for tj in (8, 4, 32):
+            _say(f"crossmap tau=2, tile {tj}")
+            ccm.set_gather_tile(tj)
+            r = ccm.crossmap_rho(_cuda(ts), idx, wt, lib_E, tau=2, tgt0=tgt0, n_tgt=n_tgt)
+            _check_rho(r.cpu().numpy(), rho_o, f"tau=2 FP32 tile {tj}", 1e-5)
+    finally:
+        ccm.set_gather_tile(0)
 
 
 def test_crossmap_at_the_largest_fp32_tile(ccm):
