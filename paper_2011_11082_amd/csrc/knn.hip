@@ -11,17 +11,19 @@
 // across lanes 0..k-1 (lane j holds the j-th nearest by (d^2, time index)).  A candidate
 // can enter only if its d^2 does not exceed the current k-th (one compare per lane, one
 // ballot per chunk); the few survivors are inserted one at a time by a DPP wave shift.
-// The chunk around the query's own time is scanned first: for autocorrelated series its
-// points are close in state space, so the k-th distance tightens at once and later
-// chunks rarely insert.  The list order is lexicographic in (d^2, time index), so the
-// scan order does not change the result and ties go to the lower index.
+// A wave walks consecutive queries and seeds each list from the previous query's
+// neighbours shifted one step (the optE scan pools the shifted lists of E - 1, E and
+// E + 1); the first query of a range scans the chunk around its own time first instead.
+// Either way the k-th distance is tight early and later chunks rarely insert.  The list
+// order is lexicographic in (d^2, time index), so the scan order does not change the
+// result and ties go to the lower index.
 //
 // Selection distances follow one canonical FP32 operation sequence (lag 0 first; one rounding per
 // subtraction, product and sum; no fused multiply-add: this file is compiled with
 // -ffp-contract=off), so the selected indices are bit-identical to any implementation
 // that follows the same sequence.  For the E scan of optE the squared distance of E is
-// the E-1 value plus one term, so one pass over the lags serves all E at once, each E
-// with its own list.
+// the E-1 value plus one term, so one pass over the lags serves every E of a group of
+// four, each E with its own list.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
