@@ -432,8 +432,10 @@ __global__ __launch_bounds__(kKnnThreads) __attribute__((amdgpu_waves_per_eu(8, 
 // to that.
 // ---------------------------------------------------------------------------------------
 // 8-wave workgroups; 16-wave ones for long series, where a workgroup's LDS (the series, the
-// bitmaps) would otherwise let fewer than kSimplexOcc waves per SIMD share a CU
+// bitmaps) would otherwise let fewer than kSimplexOcc waves per SIMD share a CU; 4-wave ones
+// for calls over many series
 constexpr int kSimplexThreads = 512;
+constexpr int kSimplexMinThreads = 256;
 constexpr int kSimplexMaxThreads = 1024;
 constexpr int kSimplexOcc = 8;
 // (group, first E, last E); every group holds an even number of lists
@@ -525,8 +527,11 @@ __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, 
   const int qlo = qbase + (E_lo - 1) * tau;
   const int qhi = L - 1 - Tp;
 
-  // lane g holds the five FP64 moment sums of E = ELO + g
-  double m_o = 0.0, m_oo = 0.0, m_p = 0.0, m_pp = 0.0, m_op = 0.0;
+  // the five FP64 moment sums of E = ELO + g accumulate in wsum[wave][g] (LDS, updated once
+  // per query by lane g), so the scan holds no moment registers
+  double* wm = &wsum[wave][0][0];
+  if (lane < kGroupE)
+    for (int c = 0; c < 5; ++c) wm[lane * 5 + c] = 0.0;
 
   // each wave walks a contiguous range of queries; every list is carried from one query to
   // the next and re-seeded with its shifted neighbours
@@ -623,21 +628,15 @@ __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, 
                                            readlane(__double2loint(pred), 32));
         if ((lane == g && acta) || (lane == g + 1 && actb)) {
           double o = obs, p = lane == g ? pred : pb;
-          m_o += o;
-          m_oo += o * o;
-          m_p += p;
-          m_pp += p * p;
-          m_op += o * p;
+          double* q = wm + lane * 5;
+          q[0] += o;
+          q[1] += o * o;
+          q[2] += p;
+          q[3] += p * p;
+          q[4] += o * p;
         }
       }
     }
-  }
-  if (lane < kGroupE) {
-    wsum[wave][lane][0] = m_o;
-    wsum[wave][lane][1] = m_oo;
-    wsum[wave][lane][2] = m_p;
-    wsum[wave][lane][3] = m_pp;
-    wsum[wave][lane][4] = m_op;
   }
 }
 
@@ -775,10 +774,15 @@ extern "C" hipError_t ccm_launch_simplex(const float* ts, int64_t ld, int L, con
            (size_t)(threads / ccm::kWave) * ((L + 31) / 32) * sizeof(uint32_t);
   };
   // 8-wave workgroups while four of them (kSimplexOcc waves per SIMD) fit a CU's LDS with the
-  // static part (under 11 KB), else 16-wave ones
-  const int threads =
-      4 * (lds_for(ccm::kSimplexThreads) + 11 * 1024) <= 160 * 1024 ? ccm::kSimplexThreads
-                                                                   : ccm::kSimplexMaxThreads;
+  // static part (under 11 KB), else 16-wave ones; calls over many series, where the chip
+  // stays full anyway, take 4-wave workgroups (eight per CU), whose waves walk longer query
+  // ranges (fewer unseeded starts)
+  auto fits = [&](int threads, int per_cu) {
+    return (size_t)per_cu * (lds_for(threads) + 11 * 1024) <= 160 * 1024;
+  };
+  const int threads = n >= 4096 && fits(ccm::kSimplexMinThreads, 8) ? ccm::kSimplexMinThreads
+                      : fits(ccm::kSimplexThreads, 4)                ? ccm::kSimplexThreads
+                                                                     : ccm::kSimplexMaxThreads;
   hipLaunchKernelGGL(ccm::simplex_kernel, dim3(n, ccm::kNGroups), dim3(threads), lds_for(threads),
                      stream, ts, ld, L, ids, E_min, E_max, tau, Tp, mode, rho64);
   hipLaunchKernelGGL(ccm::simplex_finalize_kernel, dim3((n + 255) / 256), dim3(256), 0, stream,
