@@ -19,17 +19,18 @@
 // gfx950 design: no atomics on values, fixed summation order (deterministic results).
 //   Kernel 3 (first): one workgroup per library builds the transposed neighbour relation
 //   (for each time s, the table entries whose neighbour is s, in table order), the position
-//   of every entry in it, the weights in that order, and an m-major copy of the table.
+//   of every entry in it and an m-major copy of the table (both [m][t]), and the weights in
+//   list order.
 //   Kernel 1: one workgroup per pair reads its target column once (into LDS, and a
 //   contiguous copy for kernel 2), recomputes yhat and the FP64 Pearson pieces and stores
 //   H, Gy.  Kernel 2: one thread per (pair, t) turns wbar into distance coefficients
-//   (distances recomputed in FP64 from the library series), written m-major and in the
-//   transposed order.  Kernel 4, in two steps: one thread per (pair, u) reads table row u
+//   (distances recomputed in FP64 from the library series, staged in LDS with the target
+//   column), written m-major and in the transposed order.  Kernel 4, in two steps: one thread per (pair, u) reads table row u
 //   (m-major, consecutive u in consecutive lanes) and u's transposed list (coefficients
 //   and weights contiguous) once and keeps E partial sums, one per lag; one thread per
-//   (pair, s) then combines the E + 1 partial sums that land on time s.  Kernel 5: one wave
-//   per (64 times, column hash) adds the pairs' contributions in pair order into the target
-//   and library gradients.
+//   (pair, s) then combines the E partial sums and the target term that land on time s.
+//   Kernel 5: one wave per (64 times, column hash) adds the pairs' contributions in pair
+//   order into the target and library gradients.
 //   The per-pair kernels run on XCD-aware grids (xcd_pair_block), pairs grouped by library.
 // Padding entries (-1) count as absent everywhere.
 #include <hip/hip_runtime.h>
