@@ -87,7 +87,8 @@ __device__ __forceinline__ int window_base(int t, int clo, int chi) {
 }
 
 // The series sits in LDS after kPad zeros, so x[-kPad .. -1] reads 0 and lag reads at
-// tau = 1 need no clamp.
+// tau = 1 need no clamp, and before kWave zeros, so the lanes of a last chunk that lie past
+// the final candidate read zeros (they are never admitted) without clamping their index.
 constexpr int kPad = 32;
 
 // Lag values x[sc - e tau], e = 0..NL-1, of the candidate at sc; all NL reads are issued
@@ -154,20 +155,28 @@ __device__ __forceinline__ void list_from_keys(uint64_t cand, int k1, uint64_t& 
 }
 
 // Build a sorted list of k1 + 1 entries from the distinct keys of pool lanes 0..np-1 (~0
-// where empty, np <= 64), as list_from_keys does for k1 + 1 keys: every pool key gets its
-// rank among the np keys, and the pool lanes are permuted by rank (a bijection of 0..np-1),
-// so lanes 0..k1 hold the k1 + 1 smallest in order.
+// where empty, np <= 64), as list_from_keys does for k1 + 1 keys, but over the pool's real
+// keys only: they are packed into the wave's LDS row in lane order, each gets its rank among
+// them, the other lanes take the ranks after them in lane order, and all 64 lanes are
+// permuted by rank (a bijection), so lanes 0..k1 hold the k1 + 1 smallest in order.  An
+// empty entry of rank r becomes ~0 - (63 - r): distinct, ascending, above every real key,
+// with a negative index.
 __device__ __forceinline__ void list_from_pool(uint64_t cand, int np, int k1, uint64_t& key,
                                                uint64_t& thr) {
   __shared__ uint64_t pool_keys[kMaxWaves][kWave];
   const int lane = lane_id();
-  const bool mine = lane < np;
-  const uint64_t v = !mine ? ~0ull : (cand == ~0ull ? ~0ull - (uint64_t)lane : cand);
+  const bool real = lane < np && cand != ~0ull;
+  const uint64_t rm = ballot(real);
+  const int nr = __popcll(rm);
+  const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(rm >> 32),
+                                               __builtin_amdgcn_mbcnt_lo((uint32_t)rm, 0));
   uint64_t* rk = pool_keys[__builtin_amdgcn_readfirstlane(threadIdx.x / kWave)];
-  rk[lane] = v;
+  if (real) rk[below] = cand;
   int rank = 0;
-  for (int j = 0; j < np; ++j) rank += rk[j] < v ? 1 : 0;
-  const int dst = (mine ? rank : lane) << 2;
+  for (int j = 0; j < nr; ++j) rank += rk[j] < cand ? 1 : 0;
+  rank = real ? rank : nr + (lane - below);
+  const uint64_t v = real ? cand : ~0ull - (uint64_t)(kWave - 1 - rank);
+  const int dst = rank << 2;
   const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_permute(dst, (int)(uint32_t)v);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_permute(dst, (int)(uint32_t)(v >> 32));
   key = ((uint64_t)hi << 32) | lo;
@@ -296,18 +305,18 @@ __device__ __forceinline__ void knn_query(const float* x, const uint8_t* mb, int
     thr = ~0ull;
   }
   const int wb = seeded ? hi + 1 : window_base(t, lo, hi);
+  const uint32_t xw = seeded ? 0 : kWave;
   // pass -1: the window around t (unseeded only); then every chunk in order
   for (int pass = seeded ? 0 : -1, base = lo; base <= hi;
        base += (pass < 0 ? 0 : kWave), pass = 0) {
     const int b = pass < 0 ? wb : base;
     const int s = b + lane;
-    const bool inr = s <= hi && (pass < 0 || s < wb || s >= wb + kWave);
-    const int sc = s <= hi ? s : hi;
+    const bool inr = s <= hi && (uint32_t)(s - wb) >= (pass < 0 ? 0u : xw);
     // lags 0..CHK-1 first; when no lane is still within the list's bound (d^2 only grows
     // with the lags), the chunk ends there
     constexpr int CHK = E >= 9 ? E - 4 : 0;
     float xs[E];
-    lag_values<E, TAU1>(x, sc, tau, xs);
+    lag_values<E, TAU1>(x, s, tau, xs);
     float acc = 0.0f;
 #pragma unroll
     for (int e = 0; e < CHK; ++e) {
@@ -321,7 +330,7 @@ __device__ __forceinline__ void knn_query(const float* x, const uint8_t* mb, int
         acc = acc + df * df;
       }
       bool adm = inr && s != t;
-      if (mb) adm = adm && mb[sc] != 0;   // library subsample: only marked candidates
+      if (mb) adm = adm && mb[adm ? s : 0] != 0;   // library subsample: only marked candidates
       const uint64_t cand = adm ? nkey(acc, s) : ~0ull;
       offer_chunk(cand, key, thr, E);
     }
@@ -344,8 +353,9 @@ __global__ __launch_bounds__(kKnnThreads) __attribute__((amdgpu_waves_per_eu(8, 
                                                         float* __restrict__ nbr_d2) {
   extern __shared__ float xbuf[];
   float* x = xbuf + kPad;
-  // optional candidate mask of this library (a library subsample), after the series
-  uint8_t* mb = cand_mask ? (uint8_t*)(xbuf + L + kPad) : nullptr;
+  // optional candidate mask of this library (a library subsample), after the series and its
+  // zero tail
+  uint8_t* mb = cand_mask ? (uint8_t*)(xbuf + L + kPad + kWave) : nullptr;
   __shared__ int n_adm;
   const int lib = blockIdx.x;
   const int sid = lib_ids[lib];
@@ -355,8 +365,8 @@ __global__ __launch_bounds__(kKnnThreads) __attribute__((amdgpu_waves_per_eu(8, 
   const int lo = (E - 1) * tau;           // first point
   const int hi = L - 1 - Tp;              // last point with a future
   if (threadIdx.x == 0) n_adm = 0;
-  for (int t = threadIdx.x; t < L + kPad; t += blockDim.x)
-    xbuf[t] = t < kPad || !sid_ok ? 0.0f : ts[(int64_t)(t - kPad) * ld + sid];
+  for (int t = threadIdx.x; t < L + kPad + kWave; t += blockDim.x)
+    xbuf[t] = t < kPad || t >= L + kPad || !sid_ok ? 0.0f : ts[(int64_t)(t - kPad) * ld + sid];
   if (mb)
     for (int t = threadIdx.x; t < L; t += blockDim.x) mb[t] = cand_mask[(size_t)lib * L + t];
   __syncthreads();
@@ -569,18 +579,18 @@ __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, 
     // exact path (full admissibility, 64-bit keys) only when some lane passes its bound.
     const bool win = !seeded || t - 1 < qbase + (E_hi - 1) * tau;
     const int wb = win ? window_base(t, clo, chi) : chi + 1;
+    const uint32_t xw = win ? kWave : 0;
     for (int pass = win ? -1 : 0, base = clo; base <= chi;
          base += (pass < 0 ? 0 : kWave), pass = 0) {
       const int b = pass < 0 ? wb : base;
       const int s = b + lane;
-      const bool inr = s <= chi && (pass < 0 || s < wb || s >= wb + kWave);
+      const bool inr = s <= chi && (uint32_t)(s - wb) >= (pass < 0 ? 0u : xw);
       const bool okc = inr && (half || s != t);
-      const int sc = s <= chi ? s : chi;
       // lags 0..CHK-1 first; when no candidate of the chunk is still within the group's
       // largest bound (d^2 only grows with the lags), the chunk ends there
       constexpr int CHK = ELO >= 9 ? ELO - 4 : 0;
       float xs[EHI];
-      lag_range<0, EHI, TAU1>(x, sc, tau, xs);
+      lag_range<0, EHI, TAU1>(x, s, tau, xs);
       float acc = okc ? 0.0f : INFINITY;
 #pragma unroll
       for (int e = 0; e < CHK; ++e) {
@@ -596,7 +606,7 @@ __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, 
             const int g = (e + 1 - ELO) >= 0 ? (e + 1 - ELO) : 0;
             if (ballot(acc <= tf[g]) != 0) {
               const int E = e + 1;
-              const bool adm = okc && sc >= (E - 1) * tau;
+              const bool adm = okc && s >= (E - 1) * tau;
               offer_chunk(adm ? nkey(acc, s) : ~0ull, key[g], thr[g], E);
               tf[g] = thr_float(thr[g]);
             }
@@ -643,7 +653,8 @@ __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, 
 __global__ __launch_bounds__(kSimplexMaxThreads) __attribute__((amdgpu_waves_per_eu(kSimplexOcc, kSimplexOcc))) void simplex_kernel(
     const float* __restrict__ ts, int64_t ld, int L, const int* __restrict__ ids, int E_min,
     int E_max, int tau, int Tp, int mode, double* __restrict__ rho64) {
-  // dynamic LDS: the series after kPad zeros, then each wave's bitmap over times (W words)
+  // dynamic LDS: the series between kPad and kWave zeros, then each wave's bitmap over
+  // times (W words)
   extern __shared__ float xbuf[];
   float* x = xbuf + kPad;
   __shared__ double wsum[kSimplexMaxThreads / kWave][kGroupE][5];
@@ -660,15 +671,15 @@ __global__ __launch_bounds__(kSimplexMaxThreads) __attribute__((amdgpu_waves_per
       rho64[(size_t)series * kEMax + threadIdx.x] = __builtin_nan("");
     return;
   }
-  for (int t = threadIdx.x; t < L + kPad; t += blockDim.x)
-    xbuf[t] = t < kPad ? 0.0f : ts[(int64_t)(t - kPad) * ld + sid];
+  for (int t = threadIdx.x; t < L + kPad + kWave; t += blockDim.x)
+    xbuf[t] = t < kPad || t >= L + kPad ? 0.0f : ts[(int64_t)(t - kPad) * ld + sid];
   const int W = (L + 31) / 32;
   for (int w = threadIdx.x; w < W * (int)(blockDim.x / kWave); w += blockDim.x)
-    ((uint32_t*)(xbuf + L + kPad))[w] = 0u;
+    ((uint32_t*)(xbuf + L + kPad + kWave))[w] = 0u;
   __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int nw = blockDim.x / kWave;
-  uint32_t* bm = (uint32_t*)(xbuf + L + kPad) + (size_t)wave * W;
+  uint32_t* bm = (uint32_t*)(xbuf + L + kPad + kWave) + (size_t)wave * W;
   const bool half = mode == 1;
   switch (grp) {
 #define CCM_RUN(G, LO, HI)                                                                 \
@@ -754,7 +765,7 @@ extern "C" hipError_t ccm_launch_knn(const float* ts, int64_t ld, int L, const i
   static std::atomic<uint64_t> attr{0};
   hipError_t e = ccm::allow_lds_once((const void*)ccm::knn_table_kernel, attr);
   if (e != hipSuccess) return e;
-  size_t lds = (size_t)(L + ccm::kPad) * sizeof(float) + (cand_mask ? (size_t)L : 0);
+  size_t lds = (size_t)(L + ccm::kPad + ccm::kWave) * sizeof(float) + (cand_mask ? (size_t)L : 0);
   hipLaunchKernelGGL(ccm::knn_table_kernel, dim3(n_lib), dim3(ccm::kKnnThreads), lds, stream, ts, ld,
                      L, lib_ids, lib_E, tau, Tp, k_max, cand_mask, nbr_idx, nbr_w, nbr_d2);
   return hipGetLastError();
@@ -768,9 +779,9 @@ extern "C" hipError_t ccm_launch_simplex(const float* ts, int64_t ld, int L, con
   static std::atomic<uint64_t> attr{0};
   hipError_t e = ccm::allow_lds_once((const void*)ccm::simplex_kernel, attr);
   if (e != hipSuccess) return e;
-  // dynamic LDS: the series, then each wave's bitmap over times
+  // dynamic LDS: the series and its zero tail, then each wave's bitmap over times
   auto lds_for = [&](int threads) {
-    return (size_t)(L + ccm::kPad) * sizeof(float) +
+    return (size_t)(L + ccm::kPad + ccm::kWave) * sizeof(float) +
            (size_t)(threads / ccm::kWave) * ((L + 31) / 32) * sizeof(uint32_t);
   };
   // 8-wave workgroups while four of them (kSimplexOcc waves per SIMD) fit a CU's LDS with the
