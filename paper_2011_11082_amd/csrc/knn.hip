@@ -397,8 +397,8 @@ __global__ __launch_bounds__(kKnnThreads) __attribute__((amdgpu_waves_per_eu(8, 
   // each wave walks a contiguous range of queries, seeding each list from the previous one
   const int nq = hi - lo + 1;
   const int per = (nq + nw - 1) / nw;
-  const int tb = lo + wave * per;
-  const int te = min(tb + per, hi + 1);
+  const int tb = __builtin_amdgcn_readfirstlane(lo + wave * per);   // the same in every lane
+  const int te = __builtin_amdgcn_readfirstlane(min(tb + per, hi + 1));
   uint64_t key = ~0ull, thr = ~0ull;
   for (int t = tb; t < te; ++t) {
     const bool seeded = t > tb;
@@ -547,8 +547,11 @@ __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, 
   // the next and re-seeded with its shifted neighbours
   const int nq = qhi - qlo + 1;
   const int per = nq > 0 ? (nq + nw - 1) / nw : 0;
-  const int tb = qlo + wave * per;
-  const int te = min(tb + per, qhi + 1);
+  // the range is the same in every lane; reading it from the first lane keeps the query and
+  // chunk loops under scalar control (the compiler otherwise kept their counters in vector
+  // registers and left them through exec masks)
+  const int tb = __builtin_amdgcn_readfirstlane(qlo + wave * per);
+  const int te = __builtin_amdgcn_readfirstlane(min(tb + per, qhi + 1));
   uint64_t key[NG];
   uint64_t thr[NG];
 #pragma unroll
