@@ -225,6 +225,23 @@ def test_optE_lags_and_clipped_E_ranges(ccm):
                     f"LOO E={E_min}..{E_max} tau={tau}")
 
 
+def test_optE_horizon_zero_ragged_last_chunk(ccm):
+    # Tp = 0: the last candidate is the series' last point, so the final chunk of 64
+    # candidates reaches furthest past the series (its extra lanes read the zero tail and are
+    # never admitted); lengths that leave 1, 63 and 37 candidates in that chunk for the lists
+    # of E = 1..4, whose candidates start at 0
+    w = synth.make("logistic64")
+    ids = np.arange(4)
+    for L in (65, 127, 165):
+        ts = np.ascontiguousarray(w.panel[:L])
+        for mode, omode in ((ccm.MODE_LOO, O.MODE_LOO), (ccm.MODE_HALF, O.MODE_HALF)):
+            E_max = 20 if mode == ccm.MODE_LOO else 8
+            _say(f"simplex Tp=0 L={L} mode={mode} E=1..{E_max}")
+            optE, rho = ccm.simplex_optE(_cuda(ts), ids, 1, E_max, 1, 0, mode)
+            oE, oR, _ = O.simplex_optE(ts, ids, 1, E_max, 1, 0, mode=omode)
+            _check_optE(optE.cpu().numpy(), rho.cpu().numpy(), oE, oR, f"Tp=0 L={L} mode={mode}")
+
+
 def test_optE_ratenet_sample_and_half_mode(ccm):
     w = synth.make("ratenet1024")
     ts = w.panel
