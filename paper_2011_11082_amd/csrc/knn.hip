@@ -259,19 +259,27 @@ __device__ __forceinline__ double halves32_sum(double v) {
 
 // Simplex weights of two finished lists at once: list a of E in lanes 0..E, list b of E + 1
 // in lanes 32..33 + E (lane 32 + j holds its j-th neighbour).  Each half forms its own
-// weights exactly as list_weight64 does for one list.
-__device__ __forceinline__ double pair_weight64(const float* x, int t, int nb, int E, int tau,
-                                                double& usum) {
+// weights exactly as list_weight64 does for one list.  The query's lag values come from the
+// wave's scalar copy xq (x[t - e tau]), and every lane issues the reads of its neighbour's
+// E + 1 lags together (the last lag counts in the upper half only).
+template <int E, bool TAU1, int NQ>
+__device__ __forceinline__ double pair_weight64(const float* x, const float (&xq)[NQ], int nb,
+                                                int tau, double& usum) {
+  static_assert(E + 1 <= NQ, "the query's lags cover the upper list");
   const int lane = lane_id();
   const bool up = lane >= 32;
   const int El = up ? E + 1 : E;
   const bool in = (lane & 31) <= El && nb >= 0;
+  float xs[E + 1];
+  lag_values<E + 1, TAU1>(x, in ? nb : E * tau, tau, xs);
   double dd = 0.0;
-  if (in)
-    for (int e = 0; e < El; ++e) {
-      double df = (double)x[t - e * tau] - (double)x[nb - e * tau];
-      dd += df * df;
-    }
+#pragma unroll
+  for (int e = 0; e <= E; ++e) {
+    const double df = (double)xq[e] - (double)xs[e];
+    if (e < E) dd += df * df;
+    else dd = up ? dd + df * df : dd;
+  }
+  if (!in) dd = 0.0;
   const double d = sqrt(dd);
   const double d1a = __hiloint2double(readlane(__double2hiint(d), 0), readlane(__double2loint(d), 0));
   const double d1b = __hiloint2double(readlane(__double2hiint(d), 32), readlane(__double2loint(d), 32));
@@ -522,6 +530,46 @@ __device__ __forceinline__ void seed_group(const float* x, int t, int tau, int c
   }
 }
 
+// The FP64 finish of the lists of E = ELO + G and ELO + G + 1 at query t (the second moves
+// to lanes 32..63), then the next pair.
+template <int ELO, int G, int NG, bool TAU1, int EHI>
+__device__ __forceinline__ void finish_pairs(const float* x, const float (&xq)[EHI], int t,
+                                             int tau, int Tp, int E_lo, int E_hi, int qbase,
+                                             int lane, const uint64_t (&key)[NG], float obs,
+                                             double* wm) {
+  if constexpr (G < NG) {
+    constexpr int Ea = ELO + G;
+    const bool acta = Ea >= E_lo && Ea <= E_hi && t >= qbase + (Ea - 1) * tau;
+    const bool actb = Ea + 1 >= E_lo && Ea + 1 <= E_hi && t >= qbase + Ea * tau;
+    if (acta || actb) {
+      const bool up = lane >= 32;
+      const uint32_t blo = (uint32_t)__shfl_xor((int)(uint32_t)key[G + 1], 32);
+      const uint32_t bhi = (uint32_t)__shfl_xor((int)(uint32_t)(key[G + 1] >> 32), 32);
+      const uint64_t kk = up ? (((uint64_t)bhi << 32) | blo) : key[G];
+      const int El = up ? Ea + 1 : Ea;
+      const bool act = up ? actb : acta;
+      const int li = (act && (lane & 31) <= El) ? key_idx(kk) : -1;
+      double usum;
+      double u = pair_weight64<Ea, TAU1, EHI>(x, xq, li, tau, usum);
+      double f = ((lane & 31) <= El && li >= 0) ? (double)x[li + Tp] : 0.0;
+      double pred = halves32_sum(u * f) / usum;
+      const double pb = __hiloint2double(readlane(__double2hiint(pred), 32),
+                                         readlane(__double2loint(pred), 32));
+      if ((lane == G && acta) || (lane == G + 1 && actb)) {
+        double o = obs, p = lane == G ? pred : pb;
+        double* q = wm + lane * 5;
+        q[0] += o;
+        q[1] += o * o;
+        q[2] += p;
+        q[3] += p * p;
+        q[4] += o * p;
+      }
+    }
+    finish_pairs<ELO, G + 2, NG, TAU1, EHI>(x, xq, t, tau, Tp, E_lo, E_hi, qbase, lane, key, obs,
+                                            wm);
+  }
+}
+
 template <int ELO, int EHI, bool TAU1>
 __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, int E_max, int tau,
                                               int Tp, bool half, int wave, int nw, uint32_t* bm,
@@ -620,36 +668,7 @@ __device__ __forceinline__ void simplex_group(const float* x, int L, int E_min, 
     const float obs = x[t + Tp];
     // the lists of E and E + 1 are finished together: the second moves to lanes 32..63
     static_assert(NG % 2 == 0, "lists are finished in pairs");
-#pragma unroll
-    for (int g = 0; g < NG; g += 2) {
-      const int Ea = ELO + g;
-      const bool acta = Ea >= E_lo && Ea <= E_hi && t >= qbase + (Ea - 1) * tau;
-      const bool actb = Ea + 1 >= E_lo && Ea + 1 <= E_hi && t >= qbase + Ea * tau;
-      if (acta || actb) {
-        const bool up = lane >= 32;
-        const uint32_t blo = (uint32_t)__shfl_xor((int)(uint32_t)key[g + 1], 32);
-        const uint32_t bhi = (uint32_t)__shfl_xor((int)(uint32_t)(key[g + 1] >> 32), 32);
-        const uint64_t kk = up ? (((uint64_t)bhi << 32) | blo) : key[g];
-        const int El = up ? Ea + 1 : Ea;
-        const bool act = up ? actb : acta;
-        const int li = (act && (lane & 31) <= El) ? key_idx(kk) : -1;
-        double usum;
-        double u = pair_weight64(x, t, li, Ea, tau, usum);
-        double f = ((lane & 31) <= El && li >= 0) ? (double)x[li + Tp] : 0.0;
-        double pred = halves32_sum(u * f) / usum;
-        const double pb = __hiloint2double(readlane(__double2hiint(pred), 32),
-                                           readlane(__double2loint(pred), 32));
-        if ((lane == g && acta) || (lane == g + 1 && actb)) {
-          double o = obs, p = lane == g ? pred : pb;
-          double* q = wm + lane * 5;
-          q[0] += o;
-          q[1] += o * o;
-          q[2] += p;
-          q[3] += p * p;
-          q[4] += o * p;
-        }
-      }
-    }
+    finish_pairs<ELO, 0, NG, TAU1, EHI>(x, xq, t, tau, Tp, E_lo, E_hi, qbase, lane, key, obs, wm);
   }
 }
 
